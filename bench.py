@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Benchmark of the NASGabor appearance path on one MI355X.
+
+Headline workload: NASGabor K = 8, fused forward+backward, 3 M primitives x
+16 cameras in one launch (FP32 storage, EXACT normaliser), synthetic inputs
+already resident in HBM. One step = one fused launch over the whole batch.
+Prints one JSON line; see the design doc for the byte accounting.
+
+    python bench.py [--steps K] [--warmup W] [--n N] [--norm exact|approx]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "primitive-view evals/s fwd+bwd (G/s) + % HBM peak, NASGabor K=8 vs SH deg 3"
+HBM_PEAK_GBS = 8000.0
+LOBE_BYTES_F32 = 44          # quat 16 + shape 16 + rgbw 12
+LOBE_BYTES_BF16 = 22
+PRIM_BYTES = 24              # c0 12 + means 12
+VIEW_BYTES = 12              # one rgb or grad_rgb triple
+
+
+def algorithmic_bytes(n, k, v, *, fwd=True, bwd=True, rgb_out=True, lobe_bytes=LOBE_BYTES_F32,
+                      accumulate=False):
+    """HBM bytes one launch must move at minimum (each input read once, each
+    output written once)."""
+    rd = n * (k * lobe_bytes + PRIM_BYTES)
+    b = rd
+    if bwd:
+        b += n * v * VIEW_BYTES                  # grad_rgb
+        b += n * (k * 44 + PRIM_BYTES)           # f32 gradients of every input
+        if accumulate:
+            b += n * (k * 44 + PRIM_BYTES)       # read-modify-write
+    if fwd and rgb_out:
+        b += n * v * VIEW_BYTES                  # rgb
+    return b
+
+
+def sh_bytes(n, v, *, fwd=True, bwd=True):
+    b = n * (192 + 12)                           # 48 coefficients + mean
+    if bwd:
+        b += n * v * VIEW_BYTES + n * (192 + 12)
+    if fwd:
+        b += n * v * VIEW_BYTES
+    return b
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_09794_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    if it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+# ----------------------------------------------------------------- CPU oracle
+
+def _oracle_chunk(args):
+    import oracle.nasg_ref as R
+    w, norm = args
+    R.forward_backward(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, norm, means=w.means, cams=w.cams)
+    return w.n * w.v
+
+
+def cpu_baseline(w_full, prims=8192, chunk=512, norm_code=0):
+    """Time the FP64 oracle (as written) on the first `prims` primitives of the
+    workload, split over the host's cores."""
+    import workloads as W
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    idx = np.arange(min(prims, w_full.n))
+    chunks = [(W.take_primitives(w_full, idx[i:i + chunk]), norm_code) for i in range(0, idx.size, chunk)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_chunk, chunks[:cores])                   # warm the workers
+        t0 = time.perf_counter()
+        evals = sum(pool.map(_oracle_chunk, chunks))
+        dt = time.perf_counter() - t0
+    return {"value": evals / dt / 1e9, "unit": "G evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, fused fwd+bwd on {idx.size} of {w_full.n} primitives x "
+                      f"{w_full.v} views (K={w_full.k}), {len(chunks)} chunks over {cores} "
+                      f"processes, {dt:.1f} s wall",
+            "cpu": platform.processor() or platform.machine()}
+
+
+# ----------------------------------------------------------------------- GPU
+
+def upload(w, device="cuda"):
+    import torch
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    if w.dtype == "bf16":
+        lob = {k: torch.from_numpy(getattr(w, k + "_bits").view(np.int16)).to(device).view(torch.bfloat16)
+               for k in ("quat", "shape", "rgbw")}
+    else:
+        lob = {k: t(getattr(w, k)) for k in ("quat", "shape", "rgbw")}
+    return dict(lob, c0=t(w.c0), means=t(w.means), cams=t(w.cams), grad_rgb=t(w.grad_rgb),
+                sh=t(w.sh))
+
+
+def time_launches(fn, steps, warmup):
+    """Mean ms per call of fn() over `steps` calls, HIP events on the current
+    stream (the stream the kernels are launched on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def sampled_parity(w, d, g, rgb, norm, n_sample=512, seed=0):
+    """Oracle on sampled primitives of the full-size run (all views, all lobes)."""
+    import workloads as W
+    from oracle import metrics as M
+    from oracle import nasg_ref as R
+    idx = np.sort(np.random.default_rng(seed).choice(w.n, size=min(n_sample, w.n), replace=False))
+    sub = W.take_primitives(w, idx)
+    code = R.NORM_EXACT if norm == "exact" else R.NORM_APPROX
+    ref, scale = R.forward_backward(sub.quat, sub.shape, sub.rgbw, sub.c0, sub.grad_rgb, code,
+                                    means=sub.means, cams=sub.cams)
+    ref["geom"], scale["geom"] = ref.pop("means"), scale.pop("means")
+    got = {"rgb": rgb[:, idx].cpu().numpy(), "quat": g["quat"][:, idx].cpu().numpy(),
+           "shape": g["shape"][:, idx].cpu().numpy(), "rgbw": g["rgbw"][:, :, idx].cpu().numpy(),
+           "c0": g["c0"][idx].cpu().numpy(), "geom": g["geom"][idx].cpu().numpy()}
+    return {k: M.summarize(M.scaled_error(got[k], ref[k], scale[k]))["max"] for k in got}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--views", type=int, default=16)
+    ap.add_argument("--norm", choices=["exact", "approx"], default="exact")
+    ap.add_argument("--quick", action="store_true", help="headline only (no comparisons, no CPU leg)")
+    ap.add_argument("--cpu-prims", type=int, default=8192)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the path shards by primitive with no "
+              "exchange, so --gpus N > 1 is not run (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    from paper_2606_09794_amd import autotune
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    autotune.load_cache()
+    t0 = time.perf_counter()
+    w = W.config2(n=args.n, v=args.views)
+    log(f"generated N={w.n} K={w.k} V={w.v} in {time.perf_counter() - t0:.1f}s")
+    d = upload(w)
+    n, k, v = w.n, w.k, w.v
+    g = P.nasg_grad_buffers(k, n, "cuda")
+    rgb = torch.empty((v, n, 3), device="cuda")
+
+    def fused():
+        P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"], means=d["means"],
+                        cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
+
+    ms = time_launches(fused, args.steps, args.warmup)
+    evals = n * v
+    value = evals / (ms * 1e-3) / 1e9
+    abytes = algorithmic_bytes(n, k, v)
+    achieved = abytes / (ms * 1e-3) / 1e9
+    log(f"fused fwd+bwd {ms:.3f} ms/step, {value:.2f} G evals/s, {achieved:.0f} GB/s algorithmic")
+    traffic = measured_traffic(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}")
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "G evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
+                               f"one launch, FP32 storage, {args.norm} normaliser",
+                   "primitives": n, "lobes": k, "views": v, "norm": args.norm},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": abytes,
+                     "kernel": "nasg_kernel (fused forward+backward)"},
+    }
+
+    if not args.quick:
+        cmp = {}
+        steps = max(3, args.steps // 2)
+        # separate forward and backward launches
+        def sep():
+            P.nasg_eval_fwd(d["quat"], d["shape"], d["rgbw"], d["c0"], means=d["means"],
+                            cams=d["cams"], norm=args.norm, out=rgb)
+            P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],
+                            means=d["means"], cams=d["cams"], norm=args.norm, grads=g)
+        m = time_launches(sep, steps, 1)
+        cmp["nasg_separate_fwd_then_bwd"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4)}
+        # 16 single-view launches, gradients accumulated
+        cams1 = [d["cams"][i:i + 1].contiguous() for i in range(v)]
+        gr1 = [d["grad_rgb"][i:i + 1].contiguous() for i in range(v)]
+        rgb1 = torch.empty((1, n, 3), device="cuda")
+
+        def single():
+            for i in range(v):
+                P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], gr1[i], means=d["means"],
+                                cams=cams1[i], norm=args.norm, grads=g, accumulate=i > 0, rgb_out=rgb1)
+        m = time_launches(single, max(2, steps // 4), 1)
+        cmp["nasg_16_single_view_launches"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4)}
+        # the other normaliser
+        other = "approx" if args.norm == "exact" else "exact"
+
+        def fused_other():
+            P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"], means=d["means"],
+                            cams=d["cams"], norm=other, grads=g, rgb_out=rgb)
+        m = time_launches(fused_other, steps, 1)
+        cmp[f"nasg_fused_{other}_normaliser"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4)}
+        # SH degree 3, same means / cameras / upstream gradient
+        gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
+
+        def sh():
+            P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"], grads=gsh,
+                           rgb_out=rgb)
+        m = time_launches(sh, steps, 1)
+        sb = sh_bytes(n, v)
+        cmp["sh3_fused"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4),
+                            "GB_s": round(sb / m / 1e6, 1), "hbm_frac": round(sb / m / 1e6 / HBM_PEAK_GBS, 4)}
+        # plain FP32 single-view path on the same primitives (first camera)
+        def plain():
+            P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], gr1[0], means=d["means"],
+                            cams=cams1[0], norm=args.norm, grads=g, rgb_out=rgb1)
+        m = time_launches(plain, steps, 1)
+        pb = algorithmic_bytes(n, k, 1)
+        cmp["nasg_plain_single_view"] = {"ms": round(m, 4), "G_evals_s": round(n / m / 1e6, 4),
+                                         "GB_s": round(pb / m / 1e6, 1),
+                                         "hbm_frac": round(pb / m / 1e6 / HBM_PEAK_GBS, 4)}
+        out["compare"] = cmp
+        # sampled parity of the timed configuration (rerun the headline once)
+        fused()
+        torch.cuda.synchronize()
+        out["parity_sampled_max_scaled_error"] = sampled_parity(w, d, g, rgb, args.norm)
+        log(f"parity {out['parity_sampled_max_scaled_error']}")
+        del d, g, rgb, gsh
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(w, prims=args.cpu_prims,
+                                           norm_code=0 if args.norm == "exact" else 1)
+        log(f"cpu baseline {out['cpu_baseline']['value'] * 1e3:.3f} M evals/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * nasg.h - C ABI of the NASGabor / degree-3 SH appearance evaluator for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for every primitive i and view v, the view-dependent
+ * colour of the appearance model of Section 4.2 (appearance-model equation)
+ *
+ *     rgb(i, v) = c0_i + sum_{l < K} w_{i,l} G_{i,l}(d_{i,v})
+ *
+ * with G the Normalized Anisotropic Spherical Gabor lobe of Section 5.1, and
+ * the analytic gradients of a scalar loss L = sum grad_rgb * rgb with respect
+ * to every stored input (Supplementary F, with dC^{-1}/dlambda read with a
+ * minus sign), plus a degree-3 real spherical-harmonics evaluator (Section
+ * 3.2) as the comparison model. Following the central-ray approximation of
+ * Section 5.2 there is one evaluation per primitive per view, along
+ *
+ *     d_{i,v} = (mu_i - o_v) / |mu_i - o_v|        (ray r(t) = o + t d, Section 3.1)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array pointers are DEVICE pointers owned by the caller. The library
+ *   never allocates, frees, synchronises or copies between host and device
+ *   inside the evaluation calls, and reads the argument structs only on the
+ *   host during the call (they may live on the caller's stack).
+ * - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
+ * - Sizes are 64-bit; element offsets are computed in 64 bits.
+ * - The return value is the only error channel (NASG_OK or a negative
+ *   nasg_status). Arguments are validated on the host before any launch; on
+ *   an error nothing is launched and no output is touched.
+ * - n == 0 is valid and launches nothing.
+ * - Every output is fully overwritten (NASG_GRAD_OVERWRITE) or added to
+ *   (NASG_GRAD_ACCUMULATE, gradients only). Results are bitwise
+ *   deterministic run to run: per-primitive sums over views are reduced in a
+ *   fixed order in registers and wavefront lanes, without atomics.
+ *
+ * Layouts (primitive index fastest inside each lobe; K lobes lobe-major)
+ * ---------------------------------------------------------------------
+ *   quat   [K][N][4]  lobe frame as a quaternion (w, x, y, z), any nonzero
+ *                     norm; the frame is the rotation of q/|q|: x, y, z are the
+ *                     columns of R(q/|q|) (the paper's R = [x y z], y = z x x,
+ *                     Supplementary C, with a quaternion in place of its
+ *                     three cosines).                     16 B aligned (f32)
+ *   shape  [K][N][4]  (lambda > 0, a > -1, k, zeta): bandwidth, anisotropy,
+ *                     carrier frequency and carrier phase; the carrier is
+ *                     (1 + cos(k d.x + zeta))/2 (zeta = 0 is the paper's).
+ *                                                         16 B aligned (f32)
+ *   rgbw   [K][3][N]  per-lobe RGB weight w, channel-planar
+ *   c0     [N][3]     diffuse colour (always float32)
+ *   means  [N][3], cams [V][3]     primitive centres and camera centres, or
+ *   dirs   [N][3]     one raw view direction per primitive (normalised
+ *                     inside; then V must be 1)
+ *   rgb, grad_rgb   [V][N][3] float32
+ *   sh     [16][3][N] SH coefficients, basis index l*l + l + m
+ * With NASG_BF16 storage, quat / shape / rgbw hold bfloat16 values (8 B
+ * aligned for quat / shape); arithmetic and accumulation stay float32 (frame
+ * and view geometry float64) and every gradient is written as float32 in the
+ * float32 layout above.
+ */
+#ifndef NASG_H
+#define NASG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nasg_status {
+  NASG_OK = 0,
+  NASG_ERR_NULL = -1,      /* a required pointer is NULL                      */
+  NASG_ERR_SHAPE = -2,     /* n < 0, k outside [1, NASG_MAX_LOBES], v outside
+                              [1, NASG_MAX_VIEWS], or dirs given with v != 1  */
+  NASG_ERR_ALIGN = -3,     /* a pointer is not aligned as the layout requires */
+  NASG_ERR_DTYPE = -4,     /* unknown storage dtype                           */
+  NASG_ERR_MODE = -5,      /* unknown normaliser or gradient mode             */
+  NASG_ERR_LAUNCH = -6,    /* the HIP runtime rejected a launch               */
+  NASG_ERR_WORKSPACE = -7  /* batched: workspace missing, too small or stale  */
+} nasg_status;
+
+enum { NASG_MAX_LOBES = 64, NASG_MAX_VIEWS = 4096 };
+
+typedef enum nasg_dtype { NASG_F32 = 0, NASG_BF16 = 1 } nasg_dtype;
+
+/* Normaliser of each lobe.
+ * EXACT : 1 / I, I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) (1 + cos(zeta) Psi),
+ *         Psi = 2 Lam e^{-Lam} sinhc(sqrt(Lam^2 - k^2)) / (1 - e^{-2 Lam}),
+ *         Lam = lam (1 + a): the closed-form integral of Section 5.1 (the phase
+ *         multiplies Psi by cos zeta; zeta = 0 is the printed formula).
+ * APPROX: C^{-1} = lam sqrt(1+a) / (2 pi (1 - e^{-2 lam})), the NASG
+ *         normaliser that ignores the carrier (Section 5.1, used for the
+ *         paper's results; Supplementary E/F).                                */
+typedef enum nasg_norm { NASG_NORM_EXACT = 0, NASG_NORM_APPROX = 1 } nasg_norm;
+
+typedef enum nasg_grad_mode { NASG_GRAD_OVERWRITE = 0, NASG_GRAD_ACCUMULATE = 1 } nasg_grad_mode;
+
+typedef struct nasg_params {
+  const void* quat;   /* [K][N][4]  f32 or bf16                               */
+  const void* shape;  /* [K][N][4]  f32 or bf16                               */
+  const void* rgbw;   /* [K][3][N]  f32 or bf16                               */
+  const float* c0;    /* [N][3]                                               */
+  int64_t n;          /* primitives                                           */
+  int32_t k;          /* lobes per primitive, 1..NASG_MAX_LOBES               */
+  int32_t dtype;      /* nasg_dtype of quat / shape / rgbw                    */
+} nasg_params;
+
+typedef struct nasg_views {
+  const float* means; /* [N][3]  used when dirs == NULL                       */
+  const float* cams;  /* [V][3]  used when dirs == NULL                       */
+  const float* dirs;  /* [N][3]  optional raw directions (then v must be 1)   */
+  int32_t v;          /* views, 1..NASG_MAX_VIEWS                             */
+} nasg_views;
+
+/* Gradient outputs, float32, same layouts as the inputs. Any pointer may be
+ * NULL to skip that gradient. `geom` receives dL/dmeans [N][3] (camera mode:
+ * summed over views) or dL/ddirs [N][3] (direction mode). Camera centres get
+ * no gradient.                                                               */
+typedef struct nasg_grads {
+  float* quat;        /* [K][N][4]                                            */
+  float* shape;       /* [K][N][4]  (dL/dlam, dL/da, dL/dk, dL/dzeta)        */
+  float* rgbw;        /* [K][3][N]                                            */
+  float* c0;          /* [N][3]                                               */
+  float* geom;        /* [N][3]                                               */
+} nasg_grads;
+
+/* Forward: rgb[V][N][3] = c0 + sum_l w_l G_l(d) (Section 4.2 appearance model,
+ * Section 5.1 lobe). `norm` is a nasg_norm.                                  */
+int nasg_eval_fwd(const nasg_params* p, const nasg_views* views, float* rgb,
+                  int32_t norm, void* stream);
+
+/* Backward: gradients of L = sum grad_rgb * rgb w.r.t. quat, shape, rgbw, c0
+ * and means (or dirs), following the product-rule derivatives of
+ * Supplementary F (plus the derivative of the EXACT normaliser, and
+ * dG/dd = s_x x + s_z z where dG/dx = s_x d, dG/dz = s_z d). Lobe gradients
+ * are summed over all V views of the call. If `rgb` is not NULL the forward
+ * colours are written too (fused forward+backward, one pass over the
+ * parameters). `grad_mode` is a nasg_grad_mode.                               */
+int nasg_eval_bwd(const nasg_params* p, const nasg_views* views, const float* grad_rgb,
+                  const nasg_grads* g, float* rgb, int32_t norm, int32_t grad_mode,
+                  void* stream);
+
+/* Degree-3 real SH (Section 3.2): rgb[V][N][3] = sum_{j<16} sh[j][c][i] Y_j(d),
+ * real orthonormal basis from the complex harmonics with the Condon-Shortley
+ * phase (Y_lm = sqrt2 Re Y_l^m for m > 0, sqrt2 Im Y_l^|m| for m < 0); no
+ * offset or clamp. `sh` is float32 [16][3][N], 4 B aligned.                  */
+int sh3_eval_fwd(const float* sh, int64_t n, const nasg_views* views, float* rgb,
+                 void* stream);
+
+/* Gradients of L = sum grad_rgb * rgb w.r.t. the SH coefficients (grad_sh,
+ * [16][3][N]) and the means or dirs (grad_geom, [N][3]); either may be NULL.
+ * `rgb` (nullable) also receives the forward colours.                        */
+int sh3_eval_bwd(const float* sh, int64_t n, const nasg_views* views,
+                 const float* grad_rgb, float* grad_sh, float* grad_geom, float* rgb,
+                 int32_t grad_mode, void* stream);
+
+/* Human-readable name of a status code (static storage).                    */
+const char* nasg_status_string(int status);
+
+/* ---- launch tuning --------------------------------------------------------
+ * The evaluators map each primitive to `lanes` consecutive lanes of a
+ * wavefront (1, 2, 4, 8 or 16), each lane owning up to `views_per_lane`
+ * views (lanes * views_per_lane >= V). nasg_set_tuning overrides the built-in
+ * choice for a (kernel, K, V, dtype) key; nasg_get_tuning reports the choice
+ * that a call with that key would use. kernel: 0 = NASG forward, 1 = NASG
+ * backward / fused, 2 = SH forward, 3 = SH backward. K is ignored for SH.
+ * lanes = 0 removes an override. Host-side table, not thread-safe against
+ * concurrent calls.                                                         */
+typedef struct nasg_tuning {
+  int32_t lanes;
+  int32_t views_per_lane;
+  int32_t block;       /* threads per block: 64, 128, 256, 512 or 1024        */
+} nasg_tuning;
+
+int nasg_set_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype,
+                    const nasg_tuning* t);
+int nasg_get_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype, nasg_tuning* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NASG_H */

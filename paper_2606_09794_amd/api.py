@@ -1,0 +1,219 @@
+"""Torch-facing wrappers of the C ABI and the autograd Functions.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+evaluation runs in libnasg's kernels. Inputs must be contiguous device
+tensors in the layouts of ``include/nasg.h``:
+
+    quat [K][N][4], shape [K][N][4], rgbw [K][3][N]   float32 or bfloat16
+    c0 [N][3], means [N][3], cams [V][3] or dirs [N][3], grad_rgb [V][N][3]
+    sh [16][3][N]                                       float32
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional
+
+import torch
+
+from . import _lib as L
+
+_NORMS = {"exact": L.NORM_EXACT, "approx": L.NORM_APPROX}
+
+
+def _norm_code(norm) -> int:
+    if isinstance(norm, str):
+        if norm not in _NORMS:
+            raise ValueError(f"norm must be one of {sorted(_NORMS)}")
+        return _NORMS[norm]
+    return int(norm)
+
+
+def _dev(t: Optional[torch.Tensor], name: str, dtype=torch.float32) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _views(n: int, means, cams, dirs):
+    if dirs is not None:
+        dirs = _dev(dirs, "dirs")
+        if tuple(dirs.shape) != (n, 3):
+            raise ValueError("dirs must be [N][3]")
+        return L.NasgViews(None, None, dirs.data_ptr(), 1), 1
+    means = _dev(means, "means")
+    cams = _dev(cams, "cams")
+    if means is None or cams is None:
+        raise ValueError("give either dirs or both means and cams")
+    if tuple(means.shape) != (n, 3) or cams.dim() != 2 or cams.shape[1] != 3:
+        raise ValueError("means must be [N][3] and cams [V][3]")
+    v = int(cams.shape[0])
+    return L.NasgViews(means.data_ptr(), cams.data_ptr(), None, v), v
+
+
+def _params(quat, shape, rgbw, c0):
+    dt = quat.dtype
+    if dt not in (torch.float32, torch.bfloat16):
+        raise ValueError("lobe parameters must be float32 or bfloat16")
+    _dev(quat, "quat", dt)
+    _dev(shape, "shape", dt)
+    _dev(rgbw, "rgbw", dt)
+    _dev(c0, "c0")
+    k, n = int(quat.shape[0]), int(quat.shape[1])
+    if (tuple(quat.shape) != (k, n, 4) or tuple(shape.shape) != (k, n, 4)
+            or tuple(rgbw.shape) != (k, 3, n) or tuple(c0.shape) != (n, 3)):
+        raise ValueError("expected quat/shape [K][N][4], rgbw [K][3][N], c0 [N][3]")
+    code = L.NASG_F32 if dt == torch.float32 else L.NASG_BF16
+    return L.NasgParams(quat.data_ptr(), shape.data_ptr(), rgbw.data_ptr(), c0.data_ptr(),
+                        n, k, code), k, n
+
+
+def nasg_eval_fwd(quat, shape, rgbw, c0, *, means=None, cams=None, dirs=None, norm="exact",
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-view colours rgb[V][N][3] (Section 4.2 model with NASGabor lobes)."""
+    p, k, n = _params(quat, shape, rgbw, c0)
+    vw, v = _views(n, means, cams, dirs)
+    if out is None:
+        out = torch.empty((v, n, 3), device=quat.device, dtype=torch.float32)
+    _dev(out, "out")
+    L.check(L.lib().nasg_eval_fwd(C.byref(p), C.byref(vw), _p(out), _norm_code(norm), _stream()),
+            "nasg_eval_fwd")
+    return out
+
+
+def nasg_grad_buffers(k: int, n: int, device) -> Dict[str, torch.Tensor]:
+    f = dict(device=device, dtype=torch.float32)
+    return {"quat": torch.empty((k, n, 4), **f), "shape": torch.empty((k, n, 4), **f),
+            "rgbw": torch.empty((k, 3, n), **f), "c0": torch.empty((n, 3), **f),
+            "geom": torch.empty((n, 3), **f)}
+
+
+def nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb, *, means=None, cams=None, dirs=None,
+                  norm="exact", grads: Optional[Dict[str, torch.Tensor]] = None,
+                  accumulate: bool = False, rgb_out: Optional[torch.Tensor] = None
+                  ) -> Dict[str, torch.Tensor]:
+    """Gradients of sum(grad_rgb * rgb) w.r.t. quat, shape, rgbw, c0 and the
+    means (or dirs) as float32 tensors (dict keys quat, shape, rgbw, c0, geom).
+    With ``rgb_out`` the forward colours are written in the same pass."""
+    p, k, n = _params(quat, shape, rgbw, c0)
+    vw, v = _views(n, means, cams, dirs)
+    _dev(grad_rgb, "grad_rgb")
+    if tuple(grad_rgb.shape) != (v, n, 3):
+        raise ValueError("grad_rgb must be [V][N][3]")
+    if grads is None:
+        grads = nasg_grad_buffers(k, n, quat.device)
+    for name, t in grads.items():
+        _dev(t, f"grads[{name}]")
+    _dev(rgb_out, "rgb_out")
+    g = L.NasgGrads(*(grads[x].data_ptr() if grads.get(x) is not None else None
+                      for x in ("quat", "shape", "rgbw", "c0", "geom")))
+    L.check(L.lib().nasg_eval_bwd(C.byref(p), C.byref(vw), _p(grad_rgb), C.byref(g), _p(rgb_out),
+                                  _norm_code(norm),
+                                  L.GRAD_ACCUMULATE if accumulate else L.GRAD_OVERWRITE,
+                                  _stream()), "nasg_eval_bwd")
+    return grads
+
+
+def sh3_eval_fwd(sh, *, means=None, cams=None, dirs=None,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Degree-3 SH colours rgb[V][N][3] (Section 3.2)."""
+    _dev(sh, "sh")
+    if sh.dim() != 3 or tuple(sh.shape[:2]) != (16, 3):
+        raise ValueError("sh must be [16][3][N]")
+    n = int(sh.shape[2])
+    vw, v = _views(n, means, cams, dirs)
+    if out is None:
+        out = torch.empty((v, n, 3), device=sh.device, dtype=torch.float32)
+    _dev(out, "out")
+    L.check(L.lib().sh3_eval_fwd(_p(sh), n, C.byref(vw), _p(out), _stream()), "sh3_eval_fwd")
+    return out
+
+
+def sh3_eval_bwd(sh, grad_rgb, *, means=None, cams=None, dirs=None,
+                 grads: Optional[Dict[str, torch.Tensor]] = None, accumulate: bool = False,
+                 rgb_out: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+    """Gradients w.r.t. sh and the means (or dirs): dict keys sh, geom."""
+    _dev(sh, "sh")
+    n = int(sh.shape[2])
+    vw, v = _views(n, means, cams, dirs)
+    _dev(grad_rgb, "grad_rgb")
+    if tuple(grad_rgb.shape) != (v, n, 3):
+        raise ValueError("grad_rgb must be [V][N][3]")
+    if grads is None:
+        grads = {"sh": torch.empty_like(sh), "geom": torch.empty((n, 3), device=sh.device)}
+    _dev(rgb_out, "rgb_out")
+    L.check(L.lib().sh3_eval_bwd(_p(sh), n, C.byref(vw), _p(grad_rgb), _p(grads.get("sh")),
+                                 _p(grads.get("geom")), _p(rgb_out),
+                                 L.GRAD_ACCUMULATE if accumulate else L.GRAD_OVERWRITE,
+                                 _stream()), "sh3_eval_bwd")
+    return grads
+
+
+def set_tuning(kernel: int, k: int, v: int, dtype: int, lanes: int, views_per_lane: int,
+               block: int = 256) -> None:
+    t = L.NasgTuning(lanes, views_per_lane, block)
+    L.check(L.lib().nasg_set_tuning(kernel, k, v, dtype, C.byref(t)), "nasg_set_tuning")
+
+
+def get_tuning(kernel: int, k: int, v: int, dtype: int):
+    t = L.NasgTuning()
+    L.check(L.lib().nasg_get_tuning(kernel, k, v, dtype, C.byref(t)), "nasg_get_tuning")
+    return (t.lanes, t.views_per_lane, t.block)
+
+
+# ------------------------------------------------------------------ autograd
+
+class NasgEval(torch.autograd.Function):
+    """rgb = NasgEval.apply(quat, shape, rgbw, c0, means, cams, dirs, norm).
+
+    Backward calls the analytic backward kernel; cams get no gradient. With
+    bfloat16 lobe parameters the float32 gradients are rounded to bfloat16 to
+    match the parameter dtype."""
+
+    @staticmethod
+    def forward(ctx, quat, shape, rgbw, c0, means, cams, dirs, norm="exact"):
+        rgb = nasg_eval_fwd(quat, shape, rgbw, c0, means=means, cams=cams, dirs=dirs, norm=norm)
+        ctx.save_for_backward(quat, shape, rgbw, c0, means, cams, dirs)
+        ctx.norm = norm
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        quat, shape, rgbw, c0, means, cams, dirs = ctx.saved_tensors
+        g = nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb.contiguous(), means=means, cams=cams,
+                          dirs=dirs, norm=ctx.norm)
+        dt = quat.dtype
+        gm = g["geom"] if dirs is None else None
+        gd = g["geom"] if dirs is not None else None
+        return (g["quat"].to(dt), g["shape"].to(dt), g["rgbw"].to(dt), g["c0"], gm, None, gd, None)
+
+
+class SH3Eval(torch.autograd.Function):
+    """rgb = SH3Eval.apply(sh, means, cams, dirs)."""
+
+    @staticmethod
+    def forward(ctx, sh, means, cams, dirs):
+        rgb = sh3_eval_fwd(sh, means=means, cams=cams, dirs=dirs)
+        ctx.save_for_backward(sh, means, cams, dirs)
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        sh, means, cams, dirs = ctx.saved_tensors
+        g = sh3_eval_bwd(sh, grad_rgb.contiguous(), means=means, cams=cams, dirs=dirs)
+        gm = g["geom"] if dirs is None else None
+        gd = g["geom"] if dirs is not None else None
+        return g["sh"], gm, None, gd

@@ -1,0 +1,248 @@
+// C ABI of libnasg: host-side argument validation, launch-configuration
+// choice (built-in heuristic or a caller-supplied tuning table) and dispatch
+// to the HIP kernels. No allocation, synchronisation or host<->device copy
+// happens here, so every evaluation call can be captured into a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <tuple>
+
+#include "../../include/nasg.h"
+#include "nasg_launch.hpp"
+
+namespace {
+
+using nasg::NasgArgs;
+using nasg::ShArgs;
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+struct Key {
+  int32_t kernel, k, v, dtype;
+  bool operator<(const Key& o) const {
+    return std::tie(kernel, k, v, dtype) < std::tie(o.kernel, o.k, o.v, o.dtype);
+  }
+};
+
+std::map<Key, nasg_tuning>& tuning_table() {
+  static std::map<Key, nasg_tuning> t;
+  return t;
+}
+
+bool supported(int lanes, int vpl) {
+#define NASG_OK_CASE(P_, V_) \
+  if (lanes == P_ && vpl == V_) return true;
+  NASG_FOR_EACH_CONFIG(NASG_OK_CASE)
+#undef NASG_OK_CASE
+  return false;
+}
+
+bool block_ok(int b) { return b == 64 || b == 128 || b == 256; }
+
+// Built-in choice: a primitive's views are spread over up to 16 lanes with up
+// to 4 views per lane, so per-lobe work is shared by at most 4 views and the
+// lane-group reductions stay inside one DPP row.
+nasg_tuning heuristic(int32_t v) {
+  nasg_tuning t{1, 1, 256};
+  if (v <= 1) t = {1, 1, 256};
+  else if (v == 2) t = {1, 2, 256};
+  else if (v <= 4) t = {1, 4, 256};
+  else if (v <= 8) t = {2, 4, 256};
+  else if (v <= 16) t = {4, 4, 256};
+  else t = {8, 2, 256};
+  return t;
+}
+
+nasg_tuning choose(int32_t kernel, int32_t k, int32_t v, int32_t dtype) {
+  const auto& tab = tuning_table();
+  auto it = tab.find(Key{kernel, kernel >= 2 ? 0 : k, v, kernel >= 2 ? 0 : dtype});
+  if (it != tab.end()) return it->second;
+  return heuristic(v);
+}
+
+int check_views(const nasg_views* vw, int64_t n) {
+  if (vw == nullptr) return NASG_ERR_NULL;
+  if (vw->v < 1 || vw->v > NASG_MAX_VIEWS) return NASG_ERR_SHAPE;
+  if (n == 0) return NASG_OK;
+  if (vw->dirs != nullptr) {
+    if (vw->v != 1) return NASG_ERR_SHAPE;
+    if (!aligned(vw->dirs, 4)) return NASG_ERR_ALIGN;
+  } else {
+    if (vw->means == nullptr || vw->cams == nullptr) return NASG_ERR_NULL;
+    if (!aligned(vw->means, 4) || !aligned(vw->cams, 4)) return NASG_ERR_ALIGN;
+  }
+  return NASG_OK;
+}
+
+int check_params(const nasg_params* p) {
+  if (p == nullptr) return NASG_ERR_NULL;
+  if (p->n < 0 || p->k < 1 || p->k > NASG_MAX_LOBES) return NASG_ERR_SHAPE;
+  if (p->dtype != NASG_F32 && p->dtype != NASG_BF16) return NASG_ERR_DTYPE;
+  if (p->n == 0) return NASG_OK;  // nothing is read: pointers may be NULL
+  if (p->quat == nullptr || p->shape == nullptr || p->rgbw == nullptr || p->c0 == nullptr)
+    return NASG_ERR_NULL;
+  const uintptr_t a4 = p->dtype == NASG_F32 ? 16 : 8;
+  const uintptr_t a1 = p->dtype == NASG_F32 ? 4 : 2;
+  if (!aligned(p->quat, a4) || !aligned(p->shape, a4) || !aligned(p->rgbw, a1) ||
+      !aligned(p->c0, 4))
+    return NASG_ERR_ALIGN;
+  return NASG_OK;
+}
+
+NasgArgs make_args(const nasg_params* p, const nasg_views* vw) {
+  NasgArgs a{};
+  a.quat = p->quat;
+  a.shape = p->shape;
+  a.rgbw = p->rgbw;
+  a.c0 = p->c0;
+  a.means = vw->dirs ? nullptr : vw->means;
+  a.cams = vw->dirs ? nullptr : vw->cams;
+  a.dirs = vw->dirs;
+  a.n = p->n;
+  a.k = p->k;
+  a.v = vw->v;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nasg_status_string(int status) {
+  switch (status) {
+    case NASG_OK: return "ok";
+    case NASG_ERR_NULL: return "required pointer is NULL";
+    case NASG_ERR_SHAPE: return "invalid size (n, k or v)";
+    case NASG_ERR_ALIGN: return "pointer misaligned for its layout";
+    case NASG_ERR_DTYPE: return "unknown storage dtype";
+    case NASG_ERR_MODE: return "unknown normaliser or gradient mode";
+    case NASG_ERR_LAUNCH: return "kernel launch failed";
+    case NASG_ERR_WORKSPACE: return "workspace missing, too small or stale";
+    default: return "unknown status";
+  }
+}
+
+int nasg_set_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype, const nasg_tuning* t) {
+  if (kernel < 0 || kernel > 3) return NASG_ERR_MODE;
+  if (t == nullptr) return NASG_ERR_NULL;
+  const Key key{kernel, kernel >= 2 ? 0 : k, v, kernel >= 2 ? 0 : dtype};
+  if (t->lanes == 0) {
+    tuning_table().erase(key);
+    return NASG_OK;
+  }
+  if (!supported(t->lanes, t->views_per_lane) || !block_ok(t->block)) return NASG_ERR_SHAPE;
+  tuning_table()[key] = *t;
+  return NASG_OK;
+}
+
+int nasg_get_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype, nasg_tuning* t) {
+  if (kernel < 0 || kernel > 3) return NASG_ERR_MODE;
+  if (t == nullptr) return NASG_ERR_NULL;
+  *t = choose(kernel, k, v, dtype);
+  return NASG_OK;
+}
+
+int nasg_eval_fwd(const nasg_params* p, const nasg_views* views, float* rgb, int32_t norm,
+                  void* stream) {
+  int st = check_params(p);
+  if (st != NASG_OK) return st;
+  if ((st = check_views(views, p->n)) != NASG_OK) return st;
+  if (norm != NASG_NORM_EXACT && norm != NASG_NORM_APPROX) return NASG_ERR_MODE;
+  if (p->n == 0) return NASG_OK;
+  if (rgb == nullptr) return NASG_ERR_NULL;
+  if (!aligned(rgb, 4)) return NASG_ERR_ALIGN;
+  NasgArgs a = make_args(p, views);
+  a.rgb = rgb;
+  a.norm = norm;
+  const nasg_tuning t = choose(0, p->k, views->v, p->dtype);
+  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, false,
+                                         p->dtype == NASG_BF16, t.block,
+                                         static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+int nasg_eval_bwd(const nasg_params* p, const nasg_views* views, const float* grad_rgb,
+                  const nasg_grads* g, float* rgb, int32_t norm, int32_t grad_mode,
+                  void* stream) {
+  int st = check_params(p);
+  if (st != NASG_OK) return st;
+  if ((st = check_views(views, p->n)) != NASG_OK) return st;
+  if (norm != NASG_NORM_EXACT && norm != NASG_NORM_APPROX) return NASG_ERR_MODE;
+  if (grad_mode != NASG_GRAD_OVERWRITE && grad_mode != NASG_GRAD_ACCUMULATE) return NASG_ERR_MODE;
+  if (g == nullptr) return NASG_ERR_NULL;
+  if (p->n == 0) return NASG_OK;
+  if (grad_rgb == nullptr) return NASG_ERR_NULL;
+  if (!aligned(grad_rgb, 4) || (rgb && !aligned(rgb, 4)) || (g->quat && !aligned(g->quat, 16)) ||
+      (g->shape && !aligned(g->shape, 16)) || (g->rgbw && !aligned(g->rgbw, 4)) ||
+      (g->c0 && !aligned(g->c0, 4)) || (g->geom && !aligned(g->geom, 4)))
+    return NASG_ERR_ALIGN;
+  NasgArgs a = make_args(p, views);
+  a.grad_rgb = grad_rgb;
+  a.rgb = rgb;
+  a.g_quat = g->quat;
+  a.g_shape = g->shape;
+  a.g_rgbw = g->rgbw;
+  a.g_c0 = g->c0;
+  a.g_geom = g->geom;
+  a.norm = norm;
+  a.accumulate = grad_mode == NASG_GRAD_ACCUMULATE;
+  const nasg_tuning t = choose(1, p->k, views->v, p->dtype);
+  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, true,
+                                         p->dtype == NASG_BF16, t.block,
+                                         static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+int sh3_eval_fwd(const float* sh, int64_t n, const nasg_views* views, float* rgb, void* stream) {
+  if (n < 0) return NASG_ERR_SHAPE;
+  int st = check_views(views, n);
+  if (st != NASG_OK) return st;
+  if (n == 0) return NASG_OK;
+  if (sh == nullptr || rgb == nullptr) return NASG_ERR_NULL;
+  if (!aligned(sh, 4) || !aligned(rgb, 4)) return NASG_ERR_ALIGN;
+  if (n == 0) return NASG_OK;
+  ShArgs a{};
+  a.sh = sh;
+  a.means = views->dirs ? nullptr : views->means;
+  a.cams = views->dirs ? nullptr : views->cams;
+  a.dirs = views->dirs;
+  a.rgb = rgb;
+  a.n = n;
+  a.v = views->v;
+  const nasg_tuning t = choose(2, 0, views->v, 0);
+  const hipError_t e = nasg::launch_sh(a, t.lanes, t.views_per_lane, false, t.block,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+int sh3_eval_bwd(const float* sh, int64_t n, const nasg_views* views, const float* grad_rgb,
+                 float* grad_sh, float* grad_geom, float* rgb, int32_t grad_mode, void* stream) {
+  if (n < 0) return NASG_ERR_SHAPE;
+  int st = check_views(views, n);
+  if (st != NASG_OK) return st;
+  if (grad_mode != NASG_GRAD_OVERWRITE && grad_mode != NASG_GRAD_ACCUMULATE) return NASG_ERR_MODE;
+  if (n == 0) return NASG_OK;
+  if (sh == nullptr || grad_rgb == nullptr) return NASG_ERR_NULL;
+  if (!aligned(sh, 4) || !aligned(grad_rgb, 4) || (grad_sh && !aligned(grad_sh, 4)) ||
+      (grad_geom && !aligned(grad_geom, 4)) || (rgb && !aligned(rgb, 4)))
+    return NASG_ERR_ALIGN;
+  if (n == 0) return NASG_OK;
+  ShArgs a{};
+  a.sh = sh;
+  a.means = views->dirs ? nullptr : views->means;
+  a.cams = views->dirs ? nullptr : views->cams;
+  a.dirs = views->dirs;
+  a.grad_rgb = grad_rgb;
+  a.rgb = rgb;
+  a.g_sh = grad_sh;
+  a.g_geom = grad_geom;
+  a.n = n;
+  a.v = views->v;
+  a.accumulate = grad_mode == NASG_GRAD_ACCUMULATE;
+  const nasg_tuning t = choose(3, 0, views->v, 0);
+  const hipError_t e = nasg::launch_sh(a, t.lanes, t.views_per_lane, true, t.block,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+}  // extern "C"

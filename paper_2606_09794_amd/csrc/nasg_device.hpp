@@ -1,0 +1,247 @@
+// Device-side building blocks of the NASGabor / SH-3 evaluators (gfx950).
+//
+// - storage decode for float32 / bfloat16 lobe parameters,
+// - reductions over the `P` consecutive lanes that share a primitive, done
+//   with DPP row operations (no LDS, no atomics, fixed order),
+// - the per-lobe normaliser (Section 5.1) and its log-derivatives in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nasg {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
+
+// ---------------------------------------------------------------- storage
+
+template <bool BF16>
+struct Store;
+
+template <>
+struct Store<false> {
+  __device__ static inline float4 load4(const void* p, int64_t idx) {
+    return reinterpret_cast<const float4*>(p)[idx];
+  }
+  __device__ static inline float load1(const void* p, int64_t idx) {
+    return reinterpret_cast<const float*>(p)[idx];
+  }
+};
+
+template <>
+struct Store<true> {
+  // four bfloat16 values packed little-endian in 8 bytes
+  __device__ static inline float4 load4(const void* p, int64_t idx) {
+    const uint2 u = reinterpret_cast<const uint2*>(p)[idx];
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  }
+  __device__ static inline float load1(const void* p, int64_t idx) {
+    return __uint_as_float(static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(p)[idx]) << 16);
+  }
+};
+
+// ---------------------------------------------------------- lane-group sums
+// All-reduce over aligned groups of P consecutive lanes (P <= 16, one DPP row).
+// quad_perm [1,0,3,2] and [2,3,0,1] give the quad sum; row_half_mirror pairs
+// the two quads of a half-row; row_mirror pairs the two half-rows.
+
+template <int CTRL>
+__device__ inline float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int P>
+__device__ inline float group_sum(float x) {
+  static_assert(P == 1 || P == 2 || P == 4 || P == 8 || P == 16, "lanes per primitive");
+  if constexpr (P >= 2) x += dpp_f<0xB1>(x);
+  if constexpr (P >= 4) x += dpp_f<0x4E>(x);
+  if constexpr (P >= 8) x += dpp_f<0x141>(x);
+  if constexpr (P >= 16) x += dpp_f<0x140>(x);
+  return x;
+}
+
+// ------------------------------------------------- FP64 envelope helpers
+// The envelope exponent X = ln(p E) reaches |X| ~ 1e2 where G still matters,
+// and exp amplifies an absolute error of X into a relative error of G, so X
+// is formed in FP64. The helpers below are purpose-built for that: a few FP64
+// fused multiply-adds each (FP64 FMA issues at the non-packed FP32 rate on
+// CDNA4), relative error ~1e-13, inputs restricted to the ranges that occur.
+
+constexpr double kLn2Hi = 0.693145751953125;               // 2^-11 multiple
+constexpr double kLn2Lo = 1.4286068203094172321214581765680755e-06;
+constexpr double kLog2e = 1.442695040888963407359924681001892137;
+constexpr double kSqrtHalf = 0.707106781186547524400844362104849039;
+
+// 1/x for x > 0 normal: hardware estimate plus two Newton steps.
+__device__ inline double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+
+// ln(kappa) with kappa = 1 - h/2 in (0, 1]. ln m = 2 atanh(s), s = (m-1)/(m+1),
+// summed as 2 s (1 + s^2/3 + s^4/5 + ...) with |s| <= 3 - 2 sqrt 2. Near the
+// lobe axis (kappa >= 1/sqrt 2) s = -h/(4-h) is formed from h directly, so the
+// result keeps its relative accuracy however small h is.
+__device__ inline double log_kappa(double h, double kap) {
+  const bool nearby = h <= 2.0 - 2.0 * kSqrtHalf;
+  int e;
+  double m = frexp(kap, &e);
+  const bool low = m < kSqrtHalf;
+  m = low ? 2.0 * m : m;
+  e = low ? e - 1 : e;
+  const double num = nearby ? -h : m - 1.0;
+  const double den = nearby ? 4.0 - h : m + 1.0;
+  const double s = num * rcp64(den);
+  const double z = s * s;
+  double p = 1.0 / 17.0;
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  p = fma(p, z, 1.0);
+  const double ef = nearby ? 0.0 : static_cast<double>(e);
+  return fma(ef, kLn2Hi, fma(ef, kLn2Lo, 2.0 * s * p));
+}
+
+// e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
+// with q the Taylor series of (e^r - 1)/r to r^11/12!; e^B - 1 is taken from
+// r q(r) directly when n = 0 so it stays relatively accurate for small |B|.
+__device__ inline void exp_em1(double B, double& eb, double& em1) {
+  const double n = fmax(rint(B * kLog2e), -2000.0);
+  double r = fma(-n, kLn2Hi, B);
+  r = fma(-n, kLn2Lo, r);
+  double q = 1.0 / 479001600.0;        // 1/12!
+  q = fma(q, r, 1.0 / 39916800.0);     // 1/11!
+  q = fma(q, r, 1.0 / 3628800.0);
+  q = fma(q, r, 1.0 / 362880.0);
+  q = fma(q, r, 1.0 / 40320.0);
+  q = fma(q, r, 1.0 / 5040.0);
+  q = fma(q, r, 1.0 / 720.0);
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  const double e1 = r * q;
+  if (n == 0.0) {
+    em1 = e1;
+    eb = 1.0 + e1;
+  } else {
+    eb = ldexp(1.0 + e1, static_cast<int>(n));
+    em1 = eb - 1.0;
+  }
+}
+
+// e^X as float for X <= 0: FP64 reduction X = n ln2 + r, then the hardware
+// base-2 exponential of the small remainder and an exact power-of-two scale.
+__device__ inline float exp_neg(double X) {
+  const double n = fmax(rint(X * kLog2e), -400.0);
+  double r = fma(-n, kLn2Hi, X);
+  r = fma(-n, kLn2Lo, r);
+  const float p = __builtin_amdgcn_exp2f(static_cast<float>(r * kLog2e));
+  return ldexpf(p, static_cast<int>(n));
+}
+
+// ------------------------------------------------------------- normaliser
+
+struct LobeNorm {
+  float n;        // normaliser value
+  float dl, da;   // d ln N / d lambda, d ln N / d a
+  float dk, dz;   // d ln N / d k, d ln N / d zeta (zero for the NASG normaliser)
+};
+
+// e^{-L} S(r) and e^{-L} S'(r) with S(r) = sinh(sqrt r)/sqrt r continued to
+// r < 0 as sin(sqrt(-r))/sqrt(-r); r = L^2 - k^2. Power series for |r| <= 1,
+// otherwise the overflow-free exponential form with s - L = -k^2 / (L + s).
+__device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
+  const double r = L * L - k * k;
+  if (fabs(r) <= 1.0) {
+    // 1/(2n+1)! for n = 0..13
+    constexpr double c[14] = {1.0,
+                              1.0 / 6.0,
+                              1.0 / 120.0,
+                              1.0 / 5040.0,
+                              1.0 / 362880.0,
+                              1.0 / 39916800.0,
+                              1.0 / 6227020800.0,
+                              1.0 / 1307674368000.0,
+                              1.0 / 355687428096000.0,
+                              1.0 / 121645100408832000.0,
+                              1.0 / 51090942171709440000.0,
+                              1.0 / 25852016738884976640000.0,
+                              1.0 / 15511210043330985984000000.0,
+                              1.0 / 10888869450418352160768000000.0};
+    double s = c[13], ds = 13.0 * c[13];
+#pragma unroll
+    for (int n = 12; n >= 1; --n) {
+      s = fma(s, r, c[n]);
+      ds = fma(ds, r, n * c[n]);
+    }
+    s = fma(s, r, c[0]);
+    const double e = exp(-L);
+    F = e * s;
+    dF = e * ds;
+  } else if (r > 0.0) {
+    const double s = sqrt(r);
+    const double ep = exp(-k * k / (L + s));  // e^{s - L}
+    const double em = exp(-s - L);           // e^{-s - L}
+    const double sh = 0.5 * (ep - em), ch = 0.5 * (ep + em);
+    F = sh / s;
+    dF = (s * ch - sh) / (2.0 * s * s * s);
+  } else {
+    const double t = sqrt(-r);
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    const double e = exp(-L);
+    F = e * sn / t;
+    dF = e * (sn - t * cs) / (2.0 * t * t * t);
+  }
+}
+
+// Normaliser of one lobe and the log-derivatives the backward pass needs.
+// mode 0: 1 / closed-form integral (phase multiplies Psi by cos zeta);
+// mode 1: NASG normaliser lambda sqrt(1+a) / (2 pi (1 - e^{-2 lambda})).
+__device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, int mode) {
+  const double lam = lamf, a = af;
+  const double em2l = -expm1(-2.0 * lam);       // 1 - e^{-2 lam}
+  const double sq = sqrt(1.0 + a);
+  // d/dlam ln(lam / (1 - e^{-2 lam})) = 1/lam - 2/(e^{2 lam} - 1)
+  const double dl_base = 1.0 / lam - 2.0 / expm1(2.0 * lam);
+  const double da_base = 0.5 / (1.0 + a);
+  LobeNorm out;
+  if (mode == 1) {
+    out.n = static_cast<float>(lam * sq / (2.0 * kPi * em2l));
+    out.dl = static_cast<float>(dl_base);
+    out.da = static_cast<float>(da_base);
+    out.dk = 0.f;
+    out.dz = 0.f;
+    return out;
+  }
+  const double k = kf, zeta = zf;
+  const double L = lam * (1.0 + a);
+  double F, dFs;
+  exp_sinhc(L, k, F, dFs);
+  const double D = -expm1(-2.0 * L);            // 1 - e^{-2L}
+  const double psi = 2.0 * L * F / D;
+  const double dF_dL = -F + 2.0 * L * dFs;
+  const double dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) / D - 4.0 * L * F * exp(-2.0 * L) / (D * D);
+  const double dpsi_dk = -4.0 * L * k * dFs / D;
+  double sz, cz;
+  sincos(zeta, &sz, &cz);
+  const double B = 1.0 + cz * psi;
+  // I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) * B ;  N = 1/I
+  out.n = static_cast<float>(lam * sq / (kPi * em2l * B));
+  out.dl = static_cast<float>(dl_base - cz * dpsi_dL * (1.0 + a) / B);
+  out.da = static_cast<float>(da_base - cz * dpsi_dL * lam / B);
+  out.dk = static_cast<float>(-cz * dpsi_dk / B);
+  out.dz = static_cast<float>(sz * psi / B);
+  return out;
+}
+
+}  // namespace nasg

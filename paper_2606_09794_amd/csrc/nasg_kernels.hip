@@ -1,0 +1,375 @@
+// NASGabor appearance evaluator: forward, backward and fused forward+backward
+// kernels for gfx950.
+//
+// Work mapping: each primitive owns P consecutive lanes of a wavefront; lane j
+// evaluates views v = v0 + j + P*t (t < VPL) of that primitive, so one
+// primitive's views never leave its lane group. For every lobe the lane loads
+// the lobe parameters (structure-of-arrays, coalesced across primitives),
+// builds the frame in FP64, and then loops over its views keeping the
+// per-view state (direction, upstream gradient, colour and direction-gradient
+// accumulators) in registers. Per-lobe gradient partial sums live in
+// registers, are summed over the lane group with DPP row operations and
+// written once per lobe - no atomics, fixed summation order.
+//
+// Numerics: the view direction, the frame axes and the dot products d.x, d.z,
+// h = 1 - d.z and 1 - (d.z)^2 = h (2 - h) are FP64 (the lobes reach
+// lambda (1 + a) ~ 1e6, where FP32 rounding of d.z alone moves G by ~1e-4);
+// the carrier phase is reduced in FP64 to its offset from the nearest peak or
+// zero, which keeps the carrier and its derivative relatively accurate at its
+// peaks and zeros; the envelope exponent ln(p E) is formed in
+// FP64 (exp turns its absolute error into a relative error of G) and only
+// its final exponential, the carrier's sine/cosine and all gradient factors
+// and accumulations are FP32. The normaliser and its log-derivatives are
+// FP64, once per lobe.
+//
+// Value (Section 5.1): G = N p E c, kappa = (d.z + 1)/2,
+//   tau = a (d.x)^2 / (1 - (d.z)^2), E = kappa^tau, p = exp(2 lam (E kappa - 1)),
+//   c = (1 + cos(k d.x + zeta)) / 2.
+// Gradients (Supplementary F): with ln kappa = L and E kappa = 1 + em1,
+//   dG/dlam = 2 G em1 + G dlnN/dlam            (dp/dlam = 2 p (E kappa - 1))
+//   dG/da   = G (2 lam E kappa + 1) L dtau/da + G dlnN/da
+//   dG/dk   = N p E dc/dk + G dlnN/dk,  dG/dzeta = N p E dc/dzeta + G dlnN/dzeta
+//   dG/dx   = s_x d,  s_x = G (2 lam E kappa + 1) L 2 a d.x/(1-(d.z)^2) + k N p E dc/dtheta
+//   dG/dz   = s_z d,  s_z = G [lam (1+tau) E + tau/(2 kappa)
+//                             + (2 lam E kappa + 1) L tau 2 d.z/(1-(d.z)^2)]
+//   dG/dd   = s_x x + s_z z.
+#include <hip/hip_runtime.h>
+
+#include "nasg_device.hpp"
+#include "nasg_launch.hpp"
+
+namespace nasg {
+
+template <int P, int VPL, bool BWD, bool BF16>
+__global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
+  using S = Store<BF16>;
+  const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t prim = gt / P;
+  const int j = static_cast<int>(gt & (P - 1));
+  const int64_t N = a.n;
+  const bool valid = prim < N;
+  const int64_t i = valid ? prim : N - 1;  // tail lanes compute on a real primitive, write nothing
+  const int V = a.v;
+  const int K = a.k;
+
+  const float c00 = a.c0[3 * i + 0], c01 = a.c0[3 * i + 1], c02 = a.c0[3 * i + 2];
+  double base0, base1, base2;
+  if (a.dirs != nullptr) {
+    base0 = a.dirs[3 * i + 0];
+    base1 = a.dirs[3 * i + 1];
+    base2 = a.dirs[3 * i + 2];
+  } else {
+    base0 = a.means[3 * i + 0];
+    base1 = a.means[3 * i + 1];
+    base2 = a.means[3 * i + 2];
+  }
+
+  for (int v0 = 0; v0 < V; v0 += P * VPL) {
+    // gradients of later view chunks accumulate onto the first chunk's
+    const bool acc_mode = a.accumulate || v0 > 0;
+
+    // ---- per-view state
+    double dd[VPL][3];
+    float df[VPL][3], rinv[VPL], gr[VPL][3], col[VPL][3], gdir[VPL][3];
+    bool has[VPL];
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) {
+      const int v = v0 + j + P * t;
+      has[t] = v < V;
+      double e0 = base0, e1 = base1, e2 = base2;
+      if (a.dirs == nullptr) {
+        const int vc = has[t] ? v : 0;
+        e0 -= static_cast<double>(a.cams[3 * vc + 0]);
+        e1 -= static_cast<double>(a.cams[3 * vc + 1]);
+        e2 -= static_cast<double>(a.cams[3 * vc + 2]);
+      }
+      const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
+      const double ri = 1.0 / sqrt(r2);
+      dd[t][0] = e0 * ri;
+      dd[t][1] = e1 * ri;
+      dd[t][2] = e2 * ri;
+      df[t][0] = static_cast<float>(dd[t][0]);
+      df[t][1] = static_cast<float>(dd[t][1]);
+      df[t][2] = static_cast<float>(dd[t][2]);
+      rinv[t] = static_cast<float>(ri);
+      col[t][0] = c00;
+      col[t][1] = c01;
+      col[t][2] = c02;
+      gdir[t][0] = gdir[t][1] = gdir[t][2] = 0.f;
+      if constexpr (BWD) {
+        if (has[t]) {
+          const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
+          gr[t][0] = a.grad_rgb[o + 0];
+          gr[t][1] = a.grad_rgb[o + 1];
+          gr[t][2] = a.grad_rgb[o + 2];
+        } else {
+          gr[t][0] = gr[t][1] = gr[t][2] = 0.f;
+        }
+      }
+    }
+
+    // ---- lobes
+    for (int l = 0; l < K; ++l) {
+      const int64_t li = static_cast<int64_t>(l) * N + i;
+      const float4 q = S::load4(a.quat, li);
+      const float4 sh = S::load4(a.shape, li);
+      const float w0 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 0) * N + i);
+      const float w1 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 1) * N + i);
+      const float w2 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 2) * N + i);
+      const float lam = sh.x, an = sh.y, kf = sh.z, zf = sh.w;
+
+      // frame: x = M_x(q)/|q|^2, z = M_z(q)/|q|^2 (homogeneous rotation of q)
+      const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+      const double ww = qw * qw, xx = qx * qx, yy = qy * qy, zz = qz * qz;
+      const double is = 1.0 / (ww + xx + yy + zz);
+      const double xa0 = (ww + xx - yy - zz) * is;
+      const double xa1 = 2.0 * (qx * qy + qw * qz) * is;
+      const double xa2 = 2.0 * (qx * qz - qw * qy) * is;
+      const double za0 = 2.0 * (qx * qz + qw * qy) * is;
+      const double za1 = 2.0 * (qy * qz - qw * qx) * is;
+      const double za2 = (ww - xx - yy + zz) * is;
+      const double krev = static_cast<double>(kf) * kInvTwoPi;
+      const double zrev = static_cast<double>(zf) * kInvTwoPi;
+      const LobeNorm nm = lobe_norm(lam, an, kf, zf, a.norm);
+      const float Nn = nm.n;
+      const float two_lam = 2.f * lam;
+
+      float acc_w0 = 0.f, acc_w1 = 0.f, acc_w2 = 0.f, acc_G = 0.f, acc_l = 0.f, acc_a = 0.f;
+      float acc_k = 0.f, acc_z = 0.f;
+      float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
+      const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
+                  xf2 = static_cast<float>(xa2);
+      const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
+                  zf2 = static_cast<float>(za2);
+
+#pragma unroll
+      for (int t = 0; t < VPL; ++t) {
+        if (!has[t]) continue;
+        const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
+        const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
+        const double hd = 1.0 - dzd;
+        const double kapd = 0.5 * (1.0 + dzd);
+        if (!(kapd > 0.0)) continue;  // d = -z: G = 0 and no gradient
+        const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
+        const float dx = static_cast<float>(dxd);
+        const float kap = static_cast<float>(kapd);
+        // carrier phase in revolutions, reduced to the nearest integer
+        // (theta = 2 pi (f + integer), |f| <= 1/2). The carrier is cos^2(pi f) and
+        // dc/dtheta = -sign(f) sin(pi|f|) cos(pi|f|); both are evaluated from the
+        // smaller of |f| and 1/2 - |f| so they stay relatively accurate at the
+        // carrier's peaks and zeros alike.
+        const double tr = fma(dxd, krev, zrev);
+        const double fr = tr - rint(tr);
+        const double fa = fabs(fr);
+        const bool near_peak = fa <= 0.25;
+        float sa, ca;
+        sincospif(static_cast<float>(near_peak ? fa : 0.5 - fa), &sa, &ca);
+        const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
+        const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
+        const float car = cos_f * cos_f;
+        // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
+        const bool pole = !(dend > 0.0);
+        const double rden = pole ? 0.0 : rcp64(dend);
+        const double Ld = log_kappa(hd, kapd);
+        const double ud = dxd * dxd * rden;        // tau / a
+        const double taud = static_cast<double>(an) * ud;
+        const double Ad = taud * Ld;               // ln E
+        double Ekd, em1d;
+        exp_em1(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
+        const float pE = exp_neg(fma(2.0 * static_cast<double>(lam), em1d, Ad));
+        const float L = static_cast<float>(Ld);
+        const float LR = pole ? -0.25f : static_cast<float>(Ld * rden);  // ln kappa / (1-(d.z)^2)
+        const float u = static_cast<float>(ud);
+        const float tau = static_cast<float>(taud);
+        const float em1 = static_cast<float>(em1d);
+        const float Npe = Nn * pE;
+        const float G = Npe * car;
+        col[t][0] = fmaf(w0, G, col[t][0]);
+        col[t][1] = fmaf(w1, G, col[t][1]);
+        col[t][2] = fmaf(w2, G, col[t][2]);
+        if constexpr (BWD) {
+          const float g0 = gr[t][0], g1 = gr[t][1], g2 = gr[t][2];
+          const float gG = fmaf(g0, w0, fmaf(g1, w1, g2 * w2));
+          acc_w0 = fmaf(g0, G, acc_w0);
+          acc_w1 = fmaf(g1, G, acc_w1);
+          acc_w2 = fmaf(g2, G, acc_w2);
+          const float qG = gG * G;
+          acc_G += qG;
+          acc_l = fmaf(qG, em1, acc_l);
+          const float Ek = 1.f + em1;
+          const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
+          acc_a = fmaf(qG * T2 * L, u, acc_a);
+          const float fsg = fr < 0.0 ? 1.f : -1.f;        // -sign(f)
+          const float Sth = fsg * sin_f * cos_f * Npe;    // N p E dc/dtheta
+          const float gS = gG * Sth;
+          acc_k = fmaf(gS, dx, acc_k);
+          acc_z += gS;
+          const float sx = fmaf(G * T2 * LR, 2.f * an * dx, Sth * kf);
+          const float inv2k = 0.5f / kap;
+          const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
+                                T2 * LR * tau * 2.f * static_cast<float>(dzd));
+          const float gsx = gG * sx, gsz = gG * sz;
+          ax0 = fmaf(gsx, df[t][0], ax0);
+          ax1 = fmaf(gsx, df[t][1], ax1);
+          ax2 = fmaf(gsx, df[t][2], ax2);
+          az0 = fmaf(gsz, df[t][0], az0);
+          az1 = fmaf(gsz, df[t][1], az1);
+          az2 = fmaf(gsz, df[t][2], az2);
+          gdir[t][0] = fmaf(gsx, xf0, fmaf(gsz, zf0, gdir[t][0]));
+          gdir[t][1] = fmaf(gsx, xf1, fmaf(gsz, zf1, gdir[t][1]));
+          gdir[t][2] = fmaf(gsx, xf2, fmaf(gsz, zf2, gdir[t][2]));
+        }
+      }
+
+      if constexpr (BWD) {
+        acc_w0 = group_sum<P>(acc_w0);
+        acc_w1 = group_sum<P>(acc_w1);
+        acc_w2 = group_sum<P>(acc_w2);
+        acc_G = group_sum<P>(acc_G);
+        acc_l = group_sum<P>(acc_l);
+        acc_a = group_sum<P>(acc_a);
+        acc_k = group_sum<P>(acc_k);
+        acc_z = group_sum<P>(acc_z);
+        ax0 = group_sum<P>(ax0);
+        ax1 = group_sum<P>(ax1);
+        ax2 = group_sum<P>(ax2);
+        az0 = group_sum<P>(az0);
+        az1 = group_sum<P>(az1);
+        az2 = group_sum<P>(az2);
+        if (valid) {
+          // the lane group splits the three stores
+          if (a.g_shape != nullptr && j == (1 % P)) {
+            float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
+                                    fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
+            float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
+            if (acc_mode) {
+              const float4 o = *dst;
+              gs.x += o.x; gs.y += o.y; gs.z += o.z; gs.w += o.w;
+            }
+            *dst = gs;
+          }
+          if (a.g_quat != nullptr && j == 0) {
+            // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
+            const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
+            const float fis = static_cast<float>(is);
+            const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 + zf1 * az1 + zf2 * az2);
+            float4 gq;
+            gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
+            gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
+            gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
+            gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
+            gq.x = (gq.x - rad * fw) * fis;
+            gq.y = (gq.y - rad * fx) * fis;
+            gq.z = (gq.z - rad * fy) * fis;
+            gq.w = (gq.w - rad * fz) * fis;
+            float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
+            if (acc_mode) {
+              const float4 o = *dst;
+              gq.x += o.x; gq.y += o.y; gq.z += o.z; gq.w += o.w;
+            }
+            *dst = gq;
+          }
+          if (a.g_rgbw != nullptr && j == (2 % P)) {
+            float* dst = a.g_rgbw + static_cast<int64_t>(l) * 3 * N + i;
+            if (acc_mode) {
+              acc_w0 += dst[0];
+              acc_w1 += dst[N];
+              acc_w2 += dst[2 * N];
+            }
+            dst[0] = acc_w0;
+            dst[N] = acc_w1;
+            dst[2 * N] = acc_w2;
+          }
+        }
+      }
+    }
+
+    // ---- per-view colours
+    if (a.rgb != nullptr && valid) {
+#pragma unroll
+      for (int t = 0; t < VPL; ++t) {
+        if (!has[t]) continue;
+        const int64_t o = (static_cast<int64_t>(v0 + j + P * t) * N + i) * 3;
+        a.rgb[o + 0] = col[t][0];
+        a.rgb[o + 1] = col[t][1];
+        a.rgb[o + 2] = col[t][2];
+      }
+    }
+
+    // ---- diffuse colour and mean / direction gradients
+    if constexpr (BWD) {
+      float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gm0 = 0.f, gm1 = 0.f, gm2 = 0.f;
+#pragma unroll
+      for (int t = 0; t < VPL; ++t) {
+        gc0 += gr[t][0];
+        gc1 += gr[t][1];
+        gc2 += gr[t][2];
+        // d = e/|e|: dL/de = (I - d d^T) dL/dd / |e|
+        const float pr = df[t][0] * gdir[t][0] + df[t][1] * gdir[t][1] + df[t][2] * gdir[t][2];
+        gm0 = fmaf(gdir[t][0] - pr * df[t][0], rinv[t], gm0);
+        gm1 = fmaf(gdir[t][1] - pr * df[t][1], rinv[t], gm1);
+        gm2 = fmaf(gdir[t][2] - pr * df[t][2], rinv[t], gm2);
+      }
+      gc0 = group_sum<P>(gc0);
+      gc1 = group_sum<P>(gc1);
+      gc2 = group_sum<P>(gc2);
+      gm0 = group_sum<P>(gm0);
+      gm1 = group_sum<P>(gm1);
+      gm2 = group_sum<P>(gm2);
+      if (valid && j == 0) {
+        if (a.g_c0 != nullptr) {
+          float* dst = a.g_c0 + 3 * i;
+          if (acc_mode) {
+            gc0 += dst[0];
+            gc1 += dst[1];
+            gc2 += dst[2];
+          }
+          dst[0] = gc0;
+          dst[1] = gc1;
+          dst[2] = gc2;
+        }
+        if (a.g_geom != nullptr) {
+          float* dst = a.g_geom + 3 * i;
+          if (acc_mode) {
+            gm0 += dst[0];
+            gm1 += dst[1];
+            gm2 += dst[2];
+          }
+          dst[0] = gm0;
+          dst[1] = gm1;
+          dst[2] = gm2;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ instantiation
+
+template <int P, int VPL, bool BWD, bool BF16>
+static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
+  const int64_t threads = a.n * P;
+  const int64_t grid = (threads + block - 1) / block;
+  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16>), dim3(static_cast<unsigned>(grid)),
+                     dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int P, int VPL>
+static hipError_t launch_pv(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s) {
+  if (bwd) return bf16 ? launch_one<P, VPL, true, true>(a, block, s)
+                       : launch_one<P, VPL, true, false>(a, block, s);
+  return bf16 ? launch_one<P, VPL, false, true>(a, block, s)
+              : launch_one<P, VPL, false, false>(a, block, s);
+}
+
+hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
+                       hipStream_t s) {
+#define NASG_CASE(P_, V_) \
+  if (lanes == P_ && vpl == V_) return launch_pv<P_, V_>(a, bwd, bf16, block, s);
+  NASG_FOR_EACH_CONFIG(NASG_CASE)
+#undef NASG_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nasg

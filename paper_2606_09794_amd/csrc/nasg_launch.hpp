@@ -1,0 +1,64 @@
+// Kernel argument blocks and launchers shared by the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nasg {
+
+struct NasgArgs {
+  const void* quat;
+  const void* shape;
+  const void* rgbw;
+  const float* c0;
+  const float* means;
+  const float* cams;
+  const float* dirs;
+  const float* grad_rgb;
+  float* rgb;
+  float* g_quat;
+  float* g_shape;
+  float* g_rgbw;
+  float* g_c0;
+  float* g_geom;
+  int64_t n;
+  int32_t k;
+  int32_t v;
+  int32_t norm;
+  int32_t accumulate;
+};
+
+struct ShArgs {
+  const float* sh;
+  const float* means;
+  const float* cams;
+  const float* dirs;
+  const float* grad_rgb;
+  float* rgb;
+  float* g_sh;
+  float* g_geom;
+  int64_t n;
+  int32_t v;
+  int32_t accumulate;
+};
+
+// (lanes per primitive, views per lane) pairs compiled into the library.
+#define NASG_FOR_EACH_CONFIG(X) \
+  X(1, 1)                       \
+  X(1, 2)                       \
+  X(1, 4)                       \
+  X(2, 1)                       \
+  X(2, 2)                       \
+  X(2, 4)                       \
+  X(4, 1)                       \
+  X(4, 2)                       \
+  X(4, 4)                       \
+  X(8, 1)                       \
+  X(8, 2)                       \
+  X(16, 1)
+
+hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
+                       hipStream_t s);
+hipError_t launch_sh(const ShArgs& a, int lanes, int vpl, bool bwd, int block, hipStream_t s);
+
+}  // namespace nasg

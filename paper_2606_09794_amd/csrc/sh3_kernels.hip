@@ -1,0 +1,210 @@
+// Degree-3 real spherical-harmonics appearance (Section 3.2), the comparison
+// model: rgb = sum_{j<16} c_j Y_j(d), forward and backward, same lane mapping
+// as the NASGabor kernels (P lanes per primitive, VPL views per lane).
+//
+// Basis (index l*l + l + m), real orthonormal harmonics from the complex ones
+// with the Condon-Shortley phase, written as homogeneous polynomials of the
+// unit direction. Constants are the closed-form normalisations:
+//   Y0 = 1/(2 sqrt(pi))
+//   Y1..3 = sqrt(3/(4pi)) (-y, z, -x)
+//   Y4 = sqrt(15/(4pi)) xy, Y5 = -sqrt(15/(4pi)) yz,
+//   Y6 = sqrt(5/(16pi)) (2z^2 - x^2 - y^2), Y7 = -sqrt(15/(4pi)) xz,
+//   Y8 = sqrt(15/(16pi)) (x^2 - y^2)
+//   Y9 = -sqrt(35/(32pi)) y (3x^2 - y^2), Y10 = sqrt(105/(4pi)) xyz,
+//   Y11 = -sqrt(21/(32pi)) y (4z^2 - x^2 - y^2),
+//   Y12 = sqrt(7/(16pi)) z (2z^2 - 3x^2 - 3y^2),
+//   Y13 = -sqrt(21/(32pi)) x (4z^2 - x^2 - y^2),
+//   Y14 = sqrt(105/(16pi)) z (x^2 - y^2), Y15 = -sqrt(35/(32pi)) x (x^2 - 3y^2)
+// The direction gradient of the homogeneous polynomials is projected onto the
+// sphere's tangent plane through d = e/|e|, so the choice of extension off the
+// sphere does not matter.
+#include <hip/hip_runtime.h>
+
+#include "nasg_device.hpp"
+#include "nasg_launch.hpp"
+
+namespace nasg {
+
+namespace shc {
+constexpr float c0 = 0.28209479177387814f;
+constexpr float c1 = 0.48860251190291992f;
+constexpr float c2a = 1.0925484305920792f;
+constexpr float c2b = 0.31539156525252005f;
+constexpr float c2c = 0.54627421529603959f;
+constexpr float c3a = 0.59004358992664352f;
+constexpr float c3b = 2.8906114426405538f;
+constexpr float c3c = 0.45704579946446572f;
+constexpr float c3d = 0.37317633259011540f;
+constexpr float c3e = 1.4453057213202769f;
+}  // namespace shc
+
+__device__ inline void sh_basis(float x, float y, float z, float Y[16]) {
+  using namespace shc;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = c0;
+  Y[1] = -c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = -c1 * x;
+  Y[4] = c2a * x * y;
+  Y[5] = -c2a * y * z;
+  Y[6] = c2b * (2.f * zz - xx - yy);
+  Y[7] = -c2a * x * z;
+  Y[8] = c2c * (xx - yy);
+  Y[9] = -c3a * y * (3.f * xx - yy);
+  Y[10] = c3b * x * y * z;
+  Y[11] = -c3c * y * (4.f * zz - xx - yy);
+  Y[12] = c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+  Y[13] = -c3c * x * (4.f * zz - xx - yy);
+  Y[14] = c3e * z * (xx - yy);
+  Y[15] = -c3a * x * (xx - 3.f * yy);
+}
+
+// sum_j b[j] grad Y_j(x, y, z) of the homogeneous polynomials
+__device__ inline void sh_grad(float x, float y, float z, const float b[16], float& gx,
+                               float& gy, float& gz) {
+  using namespace shc;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gx = -c1 * b[3];
+  gy = -c1 * b[1];
+  gz = c1 * b[2];
+  gx += c2a * (y * b[4] - z * b[7]) - 2.f * c2b * x * b[6] + 2.f * c2c * x * b[8];
+  gy += c2a * (x * b[4] - z * b[5]) - 2.f * c2b * y * b[6] - 2.f * c2c * y * b[8];
+  gz += -c2a * (y * b[5] + x * b[7]) + 4.f * c2b * z * b[6];
+  gx += -c3a * 6.f * x * y * b[9] + c3b * y * z * b[10] + c3c * 2.f * x * y * b[11] -
+        c3d * 6.f * x * z * b[12] - c3c * (4.f * zz - 3.f * xx - yy) * b[13] +
+        c3e * 2.f * x * z * b[14] - c3a * (3.f * xx - 3.f * yy) * b[15];
+  gy += -c3a * (3.f * xx - 3.f * yy) * b[9] + c3b * x * z * b[10] -
+        c3c * (4.f * zz - xx - 3.f * yy) * b[11] - c3d * 6.f * y * z * b[12] +
+        c3c * 2.f * x * y * b[13] - c3e * 2.f * y * z * b[14] + c3a * 6.f * x * y * b[15];
+  gz += c3b * x * y * b[10] - c3c * 8.f * y * z * b[11] +
+        c3d * (6.f * zz - 3.f * xx - 3.f * yy) * b[12] - c3c * 8.f * x * z * b[13] +
+        c3e * (xx - yy) * b[14];
+}
+
+template <int P, int VPL, bool BWD>
+__global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
+  const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t prim = gt / P;
+  const int j = static_cast<int>(gt & (P - 1));
+  const int64_t N = a.n;
+  const bool valid = prim < N;
+  const int64_t i = valid ? prim : N - 1;
+  const int V = a.v;
+
+  float cf[16][3];
+#pragma unroll
+  for (int b = 0; b < 16; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cf[b][c] = a.sh[static_cast<int64_t>(b * 3 + c) * N + i];
+
+  float gcf[16][3];
+  if constexpr (BWD) {
+#pragma unroll
+    for (int b = 0; b < 16; ++b) gcf[b][0] = gcf[b][1] = gcf[b][2] = 0.f;
+  }
+  float gm0 = 0.f, gm1 = 0.f, gm2 = 0.f;
+
+  const float* base = (a.dirs != nullptr) ? a.dirs : a.means;
+  const float b0 = base[3 * i + 0], b1 = base[3 * i + 1], b2 = base[3 * i + 2];
+
+  for (int v0 = 0; v0 < V; v0 += P * VPL) {
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) {
+      const int v = v0 + j + P * t;
+      if (v >= V) continue;
+      float e0 = b0, e1 = b1, e2 = b2;
+      if (a.dirs == nullptr) {
+        e0 -= a.cams[3 * v + 0];
+        e1 -= a.cams[3 * v + 1];
+        e2 -= a.cams[3 * v + 2];
+      }
+      const float ri = 1.f / sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+      const float x = e0 * ri, y = e1 * ri, z = e2 * ri;
+      float Y[16];
+      sh_basis(x, y, z, Y);
+      const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
+      if (a.rgb != nullptr && valid) {
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          r0 = fmaf(cf[b][0], Y[b], r0);
+          r1 = fmaf(cf[b][1], Y[b], r1);
+          r2 = fmaf(cf[b][2], Y[b], r2);
+        }
+        a.rgb[o + 0] = r0;
+        a.rgb[o + 1] = r1;
+        a.rgb[o + 2] = r2;
+      }
+      if constexpr (BWD) {
+        const float g0 = a.grad_rgb[o + 0], g1 = a.grad_rgb[o + 1], g2 = a.grad_rgb[o + 2];
+        float beta[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          gcf[b][0] = fmaf(g0, Y[b], gcf[b][0]);
+          gcf[b][1] = fmaf(g1, Y[b], gcf[b][1]);
+          gcf[b][2] = fmaf(g2, Y[b], gcf[b][2]);
+          beta[b] = fmaf(g0, cf[b][0], fmaf(g1, cf[b][1], g2 * cf[b][2]));
+        }
+        float gx, gy, gz;
+        sh_grad(x, y, z, beta, gx, gy, gz);
+        const float pr = x * gx + y * gy + z * gz;
+        gm0 = fmaf(gx - pr * x, ri, gm0);
+        gm1 = fmaf(gy - pr * y, ri, gm1);
+        gm2 = fmaf(gz - pr * z, ri, gm2);
+      }
+    }
+  }
+
+  if constexpr (BWD) {
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gcf[b][c] = group_sum<P>(gcf[b][c]);
+    gm0 = group_sum<P>(gm0);
+    gm1 = group_sum<P>(gm1);
+    gm2 = group_sum<P>(gm2);
+    if (valid) {
+      if (a.g_sh != nullptr) {
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (((b * 3 + c) & (P - 1)) != j) continue;
+            float* dst = a.g_sh + static_cast<int64_t>(b * 3 + c) * N + i;
+            *dst = a.accumulate ? *dst + gcf[b][c] : gcf[b][c];
+          }
+      }
+      if (a.g_geom != nullptr && j == 0) {
+        float* dst = a.g_geom + 3 * i;
+        if (a.accumulate) {
+          gm0 += dst[0];
+          gm1 += dst[1];
+          gm2 += dst[2];
+        }
+        dst[0] = gm0;
+        dst[1] = gm1;
+        dst[2] = gm2;
+      }
+    }
+  }
+}
+
+template <int P, int VPL, bool BWD>
+static hipError_t launch_sh_one(const ShArgs& a, int block, hipStream_t s) {
+  const int64_t threads = a.n * P;
+  const int64_t grid = (threads + block - 1) / block;
+  hipLaunchKernelGGL((sh3_kernel<P, VPL, BWD>), dim3(static_cast<unsigned>(grid)), dim3(block), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sh(const ShArgs& a, int lanes, int vpl, bool bwd, int block, hipStream_t s) {
+#define SH_CASE(P_, V_)                                                              \
+  if (lanes == P_ && vpl == V_)                                                      \
+    return bwd ? launch_sh_one<P_, V_, true>(a, block, s) : launch_sh_one<P_, V_, false>(a, block, s);
+  NASG_FOR_EACH_CONFIG(SH_CASE)
+#undef SH_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nasg

@@ -1,0 +1,52 @@
+"""Helpers shared by the GPU parity tests: upload a workload, call the oracle on
+the same stored values, compare with the scale-normalised error."""
+import numpy as np
+import torch
+
+from oracle import metrics as M
+from oracle import nasg_ref as R
+from oracle import sh3_ref as S
+
+NORMS = {"exact": R.NORM_EXACT, "approx": R.NORM_APPROX}
+
+
+def upload(w, device="cuda"):
+    """Device tensors of a workload (lobe params in their storage dtype)."""
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    if w.dtype == "bf16":
+        lob = {k: torch.from_numpy(getattr(w, k + "_bits").view(np.int16)).to(device).view(torch.bfloat16)
+               for k in ("quat", "shape", "rgbw")}
+    else:
+        lob = {k: t(getattr(w, k)) for k in ("quat", "shape", "rgbw")}
+    return dict(lob, c0=t(w.c0), means=t(w.means), cams=t(w.cams), dirs=t(w.dirs),
+                grad_rgb=t(w.grad_rgb), sh=t(w.sh))
+
+
+def geo(w):
+    return {"dirs": w.dirs} if w.dirs is not None else {"means": w.means, "cams": w.cams}
+
+
+def dgeo(d):
+    return {"dirs": d["dirs"]} if d["dirs"] is not None else {"means": d["means"], "cams": d["cams"]}
+
+
+def oracle_nasg(w, norm):
+    out, scale = R.forward_backward(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, NORMS[norm], **geo(w))
+    key = "dirs" if w.dirs is not None else "means"
+    out["geom"], scale["geom"] = out.pop(key), scale.pop(key)
+    return out, scale
+
+
+def oracle_sh(w):
+    out, scale = S.forward_backward(w.sh, w.grad_rgb, **geo(w))
+    key = "dirs" if w.dirs is not None else "means"
+    out["geom"], scale["geom"] = out.pop(key), scale.pop(key)
+    return out, scale
+
+
+def compare(got, ref, scale, name, tol):
+    e = M.scaled_error(got, ref, scale)
+    s = M.summarize(e)
+    assert np.isfinite(np.asarray(got)).all(), f"{name}: non-finite values"
+    assert s["max"] <= tol, f"{name}: scaled error {s} above {tol}"
+    return s

@@ -1,0 +1,121 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/nasg.h, and rejects invalid arguments on the host before
+any launch (fake device addresses are never dereferenced on these paths)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2606_09794_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "nasg.h")
+FAKE = 0x10000          # aligned fake device address (validation fails before use)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(nasg_\w+|sh3_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_match_header(lib):
+    names = declared_functions()
+    assert {"nasg_eval_fwd", "nasg_eval_bwd", "sh3_eval_fwd", "sh3_eval_bwd"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.EXPORTS, n
+
+
+def params(**kw):
+    d = dict(quat=FAKE, shape=FAKE, rgbw=FAKE, c0=FAKE, n=10, k=4, dtype=0)
+    d.update(kw)
+    return L.NasgParams(**d)
+
+
+def views(**kw):
+    d = dict(means=FAKE, cams=FAKE, dirs=None, v=2)
+    d.update(kw)
+    return L.NasgViews(**d)
+
+
+def fwd(lib, p, v, rgb=FAKE, norm=0):
+    return lib.nasg_eval_fwd(C.byref(p) if p is not None else None,
+                             C.byref(v) if v is not None else None, rgb, norm, None)
+
+
+@pytest.mark.parametrize("case,code", [
+    (dict(p=None), -1), (dict(k=0), -2), (dict(k=65), -2), (dict(n=-1), -2), (dict(dtype=2), -4),
+    (dict(quat=None), -1), (dict(quat=FAKE + 4), -3), (dict(c0=FAKE + 2), -3),
+    (dict(v=0), -2), (dict(v=5000), -2), (dict(dirs=FAKE, v=2), -2), (dict(cams=None), -1),
+    (dict(rgb=None), -1), (dict(rgb=FAKE + 1), -3), (dict(norm=7), -5),
+])
+def test_fwd_rejects(lib, case, code):
+    case = dict(case)
+    if "p" in case:
+        assert fwd(lib, None, views()) == code
+        return
+    vkeys = {"v", "dirs", "cams", "means"}
+    pk = {k: v for k, v in case.items() if k not in vkeys | {"rgb", "norm"}}
+    vk = {k: v for k, v in case.items() if k in vkeys}
+    extra = {k: v for k, v in case.items() if k in ("rgb", "norm")}
+    assert fwd(lib, params(**pk), views(**vk), **extra) == code
+
+
+def test_bf16_alignment_is_8_bytes(lib):
+    p = params(dtype=1, quat=FAKE + 8, shape=FAKE + 8, rgbw=FAKE + 2)
+    # valid alignment for bf16: reaches the mode check and stops there
+    assert fwd(lib, p, views(), norm=9) == -5
+    assert fwd(lib, params(dtype=1, quat=FAKE + 4), views(), norm=0) == -3
+
+
+def test_empty_input_needs_no_pointers(lib):
+    p = L.NasgParams(None, None, None, None, 0, 4, 0)
+    v = L.NasgViews(None, None, None, 3)
+    assert lib.nasg_eval_fwd(C.byref(p), C.byref(v), None, 0, None) == 0
+    g = L.NasgGrads()
+    assert lib.nasg_eval_bwd(C.byref(p), C.byref(v), None, C.byref(g), None, 0, 0, None) == 0
+    assert lib.sh3_eval_fwd(None, 0, C.byref(v), None, None) == 0
+    assert lib.sh3_eval_bwd(None, 0, C.byref(v), None, None, None, None, 0, None) == 0
+
+
+def test_bwd_rejects(lib):
+    p, v, g = params(), views(), L.NasgGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    bwd = lambda **kw: lib.nasg_eval_bwd(C.byref(p), C.byref(v), kw.get("grad_rgb", FAKE),  # noqa: E731
+                                         kw.get("g", C.byref(g)), kw.get("rgb", None),
+                                         kw.get("norm", 0), kw.get("mode", 0), None)
+    assert bwd(mode=3) == -5
+    assert bwd(norm=-1) == -5
+    assert bwd(grad_rgb=None) == -1
+    assert bwd(g=None) == -1
+    g2 = L.NasgGrads(FAKE + 4, FAKE, FAKE, FAKE, FAKE)
+    assert bwd(g=C.byref(g2)) == -3
+
+
+def test_sh_rejects(lib):
+    v = views()
+    assert lib.sh3_eval_fwd(None, 5, C.byref(v), FAKE, None) == -1
+    assert lib.sh3_eval_fwd(FAKE, -1, C.byref(v), FAKE, None) == -2
+    assert lib.sh3_eval_fwd(FAKE + 1, 5, C.byref(v), FAKE, None) == -3
+    assert lib.sh3_eval_bwd(FAKE, 5, C.byref(v), FAKE, None, None, None, 2, None) == -5
+
+
+def test_status_strings_and_tuning(lib):
+    for code in range(-7, 1):
+        assert lib.nasg_status_string(code)
+    t = L.NasgTuning(3, 1, 256)
+    assert lib.nasg_set_tuning(1, 8, 16, 0, C.byref(t)) == -2      # 3 lanes unsupported
+    t = L.NasgTuning(4, 2, 128)
+    assert lib.nasg_set_tuning(1, 8, 16, 0, C.byref(t)) == 0
+    out = L.NasgTuning()
+    assert lib.nasg_get_tuning(1, 8, 16, 0, C.byref(out)) == 0
+    assert (out.lanes, out.views_per_lane, out.block) == (4, 2, 128)
+    assert lib.nasg_set_tuning(1, 8, 16, 0, C.byref(L.NasgTuning(0, 0, 0))) == 0
+    assert lib.nasg_get_tuning(1, 8, 16, 0, C.byref(out)) == 0
+    assert (out.lanes, out.views_per_lane) == (4, 4)
+    assert lib.nasg_set_tuning(9, 8, 16, 0, C.byref(t)) == -5
