@@ -153,6 +153,62 @@ int sh3_eval_bwd(const float* sh, int64_t n, const nasg_views* views,
                  const float* grad_rgb, float* grad_sh, float* grad_geom, float* rgb,
                  int32_t grad_mode, void* stream);
 
+/* ---- uneven multi-scene batches -------------------------------------------
+ * Many independent scenes (different N, K and V), each evaluated exactly as
+ * nasg_eval_bwd with a non-NULL rgb would (fused forward+backward, gradients
+ * summed over that scene's views), in ONE persistent launch: the scenes are
+ * cut into tiles of primitives, the tiles are ordered by cost (tile size x K x
+ * V, largest first) and a grid of `blocks_per_cu` blocks per compute unit
+ * pulls them from a device work queue. Gradient sums stay per primitive in
+ * registers and lanes (the queue counter is the only atomic). Lobe parameters
+ * must be float32 (NASG_F32).
+ *
+ * Use: nasg_batched_workspace_bytes -> caller allocates device memory ->
+ * nasg_batched_plan (host side: validates every scene, builds the tile list,
+ * copies it to the workspace and waits for that copy; not capturable) ->
+ * nasg_batched_run any number of times (launches only: capturable into a
+ * hipGraph). A plan stays valid while the workspace and every scene buffer
+ * stay allocated; re-planning into the same workspace makes older nasg_batch
+ * handles stale, and a stale handle's run does nothing on the device.       */
+typedef struct nasg_scene {
+  nasg_params p;          /* dtype must be NASG_F32                           */
+  nasg_views views;
+  const float* grad_rgb;  /* [V][N][3]                                        */
+  nasg_grads g;           /* as for nasg_eval_bwd (NULL entries skipped)      */
+  float* rgb;             /* [V][N][3] or NULL                                */
+} nasg_scene;
+
+typedef struct nasg_batch_tuning {
+  int32_t tile_iters;     /* 256-thread block passes per tile, 1..64          */
+  int32_t blocks_per_cu;  /* persistent blocks per compute unit, 1..8         */
+} nasg_batch_tuning;
+
+typedef struct nasg_batch { /* filled by nasg_batched_plan                    */
+  void* workspace;
+  size_t bytes;
+  int32_t n_items;        /* tiles in the work list                           */
+  int32_t n_scenes;
+  int32_t grid;           /* persistent blocks launched by nasg_batched_run   */
+  int32_t norm;
+  uint64_t token;         /* identifies the plan written to the workspace     */
+} nasg_batch;
+
+/* Device bytes needed for the plan of these scenes (host-side computation;
+ * `t` may be NULL for the defaults: 4 tile passes, 2 blocks per CU).        */
+size_t nasg_batched_workspace_bytes(const nasg_scene* scenes, int32_t n_scenes,
+                                    const nasg_batch_tuning* t);
+
+/* Validate the scenes (same rules as nasg_eval_bwd), build and upload the
+ * tile list into `workspace` (device, >= nasg_batched_workspace_bytes) on
+ * `stream`, wait for the upload, and describe the plan in *out.              */
+int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
+                      const nasg_batch_tuning* t, void* workspace, size_t ws_bytes,
+                      nasg_batch* out, void* stream);
+
+/* Run a plan: one queue-reset kernel and one persistent kernel on `stream`.
+ * No allocation, copy or synchronisation: capturable into a hipGraph.       */
+int nasg_batched_run(const nasg_batch* b, void* stream);
+
 /* Human-readable name of a status code (static storage).                    */
 const char* nasg_status_string(int status);
 

@@ -5,6 +5,7 @@ The compute path is libnasg.so (hand-written HIP for gfx950, C ABI in
 ``python -m paper_2606_09794_amd.build``.
 """
 from .api import (  # noqa: F401
+    NasgBatchPlan,
     NasgEval,
     SH3Eval,
     get_tuning,

@@ -33,6 +33,21 @@ class NasgGrads(C.Structure):
                 ("c0", C.c_void_p), ("geom", C.c_void_p)]
 
 
+class NasgScene(C.Structure):
+    _fields_ = [("p", NasgParams), ("views", NasgViews), ("grad_rgb", C.c_void_p),
+                ("g", NasgGrads), ("rgb", C.c_void_p)]
+
+
+class NasgBatchTuning(C.Structure):
+    _fields_ = [("tile_iters", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
+class NasgBatch(C.Structure):
+    _fields_ = [("workspace", C.c_void_p), ("bytes", C.c_size_t), ("n_items", C.c_int32),
+                ("n_scenes", C.c_int32), ("grid", C.c_int32), ("norm", C.c_int32),
+                ("token", C.c_uint64)]
+
+
 class NasgTuning(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("views_per_lane", C.c_int32), ("block", C.c_int32)]
 
@@ -47,6 +62,12 @@ EXPORTS = {
                                C.c_void_p]),
     "sh3_eval_bwd": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(NasgViews), C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "nasg_batched_workspace_bytes": (C.c_size_t, [C.POINTER(NasgScene), C.c_int32,
+                                                  C.POINTER(NasgBatchTuning)]),
+    "nasg_batched_plan": (C.c_int, [C.POINTER(NasgScene), C.c_int32, C.c_int32,
+                                    C.POINTER(NasgBatchTuning), C.c_void_p, C.c_size_t,
+                                    C.POINTER(NasgBatch), C.c_void_p]),
+    "nasg_batched_run": (C.c_int, [C.POINTER(NasgBatch), C.c_void_p]),
     "nasg_status_string": (C.c_char_p, [C.c_int]),
     "nasg_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(NasgTuning)]),

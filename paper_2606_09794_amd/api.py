@@ -162,6 +162,50 @@ def sh3_eval_bwd(sh, grad_rgb, *, means=None, cams=None, dirs=None,
     return grads
 
 
+class NasgBatchPlan:
+    """A planned multi-scene fused forward+backward (one persistent launch).
+
+    ``scenes`` is a list of dicts with device tensors quat, shape, rgbw, c0,
+    means, cams, grad_rgb, the float32 gradient buffers ``grads`` (dict as
+    returned by nasg_grad_buffers) and optionally ``rgb`` [V][N][3]. The plan
+    keeps references to every tensor it points at; ``run()`` only launches
+    kernels and can be captured into a CUDA/HIP graph."""
+
+    def __init__(self, scenes, norm="exact", tile_iters=4, blocks_per_cu=2):
+        arr = (L.NasgScene * len(scenes))()
+        self._keep = []
+        for idx, sc in enumerate(scenes):
+            p, k, n = _params(sc["quat"], sc["shape"], sc["rgbw"], sc["c0"])
+            vw, v = _views(n, sc.get("means"), sc.get("cams"), sc.get("dirs"))
+            _dev(sc["grad_rgb"], "grad_rgb")
+            if tuple(sc["grad_rgb"].shape) != (v, n, 3):
+                raise ValueError("grad_rgb must be [V][N][3]")
+            g = sc["grads"]
+            arr[idx] = L.NasgScene(p, vw, sc["grad_rgb"].data_ptr(),
+                                   L.NasgGrads(*(g[x].data_ptr() if g.get(x) is not None else None
+                                                 for x in ("quat", "shape", "rgbw", "c0", "geom"))),
+                                   sc["rgb"].data_ptr() if sc.get("rgb") is not None else None)
+            self._keep.append(sc)
+        self._scenes = arr
+        tun = L.NasgBatchTuning(tile_iters, blocks_per_cu)
+        nbytes = L.lib().nasg_batched_workspace_bytes(arr, len(scenes), C.byref(tun))
+        if nbytes == 0 and len(scenes) > 0:
+            raise ValueError("invalid scenes or tuning for a batched plan")
+        dev = scenes[0]["quat"].device if scenes else torch.device("cuda")
+        self.workspace = torch.empty(max(nbytes, 64), dtype=torch.uint8, device=dev)
+        self.batch = L.NasgBatch()
+        L.check(L.lib().nasg_batched_plan(arr, len(scenes), _norm_code(norm), C.byref(tun),
+                                          C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                          C.byref(self.batch), _stream()), "nasg_batched_plan")
+
+    @property
+    def n_items(self) -> int:
+        return self.batch.n_items
+
+    def run(self) -> None:
+        L.check(L.lib().nasg_batched_run(C.byref(self.batch), _stream()), "nasg_batched_run")
+
+
 def set_tuning(kernel: int, k: int, v: int, dtype: int, lanes: int, views_per_lane: int,
                block: int = 256) -> None:
     t = L.NasgTuning(lanes, views_per_lane, block)

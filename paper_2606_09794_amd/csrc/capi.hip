@@ -4,8 +4,12 @@
 // happens here, so every evaluation call can be captured into a hipGraph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <tuple>
+#include <vector>
 
 #include "../../include/nasg.h"
 #include "nasg_launch.hpp"
@@ -104,6 +108,41 @@ NasgArgs make_args(const nasg_params* p, const nasg_views* vw) {
   return a;
 }
 
+int check_grad_ptrs(const float* grad_rgb, const nasg_grads* g, const float* rgb) {
+  if (grad_rgb == nullptr || g == nullptr) return NASG_ERR_NULL;
+  if (!aligned(grad_rgb, 4) || (rgb && !aligned(rgb, 4)) || (g->quat && !aligned(g->quat, 16)) ||
+      (g->shape && !aligned(g->shape, 16)) || (g->rgbw && !aligned(g->rgbw, 4)) ||
+      (g->c0 && !aligned(g->c0, 4)) || (g->geom && !aligned(g->geom, 4)))
+    return NASG_ERR_ALIGN;
+  return NASG_OK;
+}
+
+// ---- persistent batches
+int batch_variant(int32_t v) { return v <= 1 ? 0 : (v <= 4 ? 1 : 2); }
+
+struct BatchLayout {
+  size_t items_off;
+  size_t total;
+  int64_t n_items;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+BatchLayout batch_layout(const nasg_scene* sc, int32_t n, int32_t tile_iters) {
+  BatchLayout L{};
+  L.items_off = align_up(sizeof(nasg::BatchHeader) + sizeof(nasg::BatchScene) * n, 64);
+  for (int32_t s = 0; s < n; ++s) {
+    const int64_t tile = static_cast<int64_t>(tile_iters) * (256 / nasg::kBatchLanes[batch_variant(sc[s].views.v)]);
+    L.n_items += (sc[s].p.n + tile - 1) / tile;
+  }
+  L.total = L.items_off + sizeof(nasg::BatchItem) * static_cast<size_t>(L.n_items);
+  return L;
+}
+
+nasg_batch_tuning batch_defaults(const nasg_batch_tuning* t) {
+  return t ? *t : nasg_batch_tuning{4, 2};
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,11 +210,7 @@ int nasg_eval_bwd(const nasg_params* p, const nasg_views* views, const float* gr
   if (grad_mode != NASG_GRAD_OVERWRITE && grad_mode != NASG_GRAD_ACCUMULATE) return NASG_ERR_MODE;
   if (g == nullptr) return NASG_ERR_NULL;
   if (p->n == 0) return NASG_OK;
-  if (grad_rgb == nullptr) return NASG_ERR_NULL;
-  if (!aligned(grad_rgb, 4) || (rgb && !aligned(rgb, 4)) || (g->quat && !aligned(g->quat, 16)) ||
-      (g->shape && !aligned(g->shape, 16)) || (g->rgbw && !aligned(g->rgbw, 4)) ||
-      (g->c0 && !aligned(g->c0, 4)) || (g->geom && !aligned(g->geom, 4)))
-    return NASG_ERR_ALIGN;
+  if ((st = check_grad_ptrs(grad_rgb, g, rgb)) != NASG_OK) return st;
   NasgArgs a = make_args(p, views);
   a.grad_rgb = grad_rgb;
   a.rgb = rgb;
@@ -242,6 +277,116 @@ int sh3_eval_bwd(const float* sh, int64_t n, const nasg_views* views, const floa
   const nasg_tuning t = choose(3, 0, views->v, 0);
   const hipError_t e = nasg::launch_sh(a, t.lanes, t.views_per_lane, true, t.block,
                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+size_t nasg_batched_workspace_bytes(const nasg_scene* scenes, int32_t n_scenes,
+                                    const nasg_batch_tuning* t) {
+  if (n_scenes < 0 || (n_scenes > 0 && scenes == nullptr)) return 0;
+  const nasg_batch_tuning tt = batch_defaults(t);
+  if (tt.tile_iters < 1 || tt.tile_iters > 64) return 0;
+  for (int32_t s = 0; s < n_scenes; ++s)
+    if (scenes[s].p.n < 0 || scenes[s].views.v < 1) return 0;
+  return batch_layout(scenes, n_scenes, tt.tile_iters).total;
+}
+
+int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
+                      const nasg_batch_tuning* t, void* workspace, size_t ws_bytes,
+                      nasg_batch* out, void* stream) {
+  if (out == nullptr || (n_scenes > 0 && scenes == nullptr)) return NASG_ERR_NULL;
+  if (n_scenes < 0) return NASG_ERR_SHAPE;
+  if (norm != NASG_NORM_EXACT && norm != NASG_NORM_APPROX) return NASG_ERR_MODE;
+  const nasg_batch_tuning tt = batch_defaults(t);
+  if (tt.tile_iters < 1 || tt.tile_iters > 64 || tt.blocks_per_cu < 1 || tt.blocks_per_cu > 8)
+    return NASG_ERR_SHAPE;
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    const nasg_scene& sc = scenes[s];
+    int st = check_params(&sc.p);
+    if (st != NASG_OK) return st;
+    if (sc.p.dtype != NASG_F32) return NASG_ERR_DTYPE;
+    if ((st = check_views(&sc.views, sc.p.n)) != NASG_OK) return st;
+    if (sc.p.n > 0 && (st = check_grad_ptrs(sc.grad_rgb, &sc.g, sc.rgb)) != NASG_OK) return st;
+  }
+  const BatchLayout L = batch_layout(scenes, n_scenes, tt.tile_iters);
+  if (L.n_items > INT32_MAX) return NASG_ERR_SHAPE;
+  if (workspace == nullptr) return NASG_ERR_WORKSPACE;
+  if (!aligned(workspace, 64) || ws_bytes < L.total) return NASG_ERR_WORKSPACE;
+
+  static std::atomic<uint64_t> serial{0};
+  const uint64_t token =
+      (static_cast<uint64_t>(std::chrono::steady_clock::now().time_since_epoch().count()) << 16) ^
+      (++serial);
+
+  std::vector<unsigned char> host(L.total, 0);
+  auto* hdr = reinterpret_cast<nasg::BatchHeader*>(host.data());
+  hdr->token = token;
+  hdr->n_items = static_cast<int32_t>(L.n_items);
+  hdr->n_scenes = n_scenes;
+  hdr->counter = 0;
+  auto* bs = reinterpret_cast<nasg::BatchScene*>(host.data() + sizeof(nasg::BatchHeader));
+  struct Tile {
+    double cost;
+    nasg::BatchItem item;
+  };
+  std::vector<Tile> tiles;
+  tiles.reserve(static_cast<size_t>(L.n_items));
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    const nasg_scene& sc = scenes[s];
+    NasgArgs a = make_args(&sc.p, &sc.views);
+    a.grad_rgb = sc.grad_rgb;
+    a.rgb = sc.rgb;
+    a.g_quat = sc.g.quat;
+    a.g_shape = sc.g.shape;
+    a.g_rgbw = sc.g.rgbw;
+    a.g_c0 = sc.g.c0;
+    a.g_geom = sc.g.geom;
+    a.norm = norm;
+    a.accumulate = 0;
+    bs[s].args = a;
+    bs[s].variant = batch_variant(sc.views.v);
+    bs[s].tile_iters = tt.tile_iters;
+    const int64_t tile = static_cast<int64_t>(tt.tile_iters) * (256 / nasg::kBatchLanes[bs[s].variant]);
+    for (int64_t st0 = 0; st0 < sc.p.n; st0 += tile) {
+      const int64_t cnt = std::min(tile, sc.p.n - st0);
+      tiles.push_back({static_cast<double>(cnt) * sc.p.k * std::max(1, sc.views.v),
+                       nasg::BatchItem{s, 0, st0}});
+    }
+  }
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
+  auto* items = reinterpret_cast<nasg::BatchItem*>(host.data() + L.items_off);
+  for (size_t k = 0; k < tiles.size(); ++k) items[k] = tiles[k].item;
+
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(workspace, host.data(), L.total, hipMemcpyHostToDevice, hs) != hipSuccess)
+    return NASG_ERR_LAUNCH;
+  if (hipStreamSynchronize(hs) != hipSuccess) return NASG_ERR_LAUNCH;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return NASG_ERR_LAUNCH;
+  out->workspace = workspace;
+  out->bytes = L.total;
+  out->n_items = static_cast<int32_t>(L.n_items);
+  out->n_scenes = n_scenes;
+  out->grid = std::max(1, cus * tt.blocks_per_cu);
+  out->norm = norm;
+  out->token = token;
+  return NASG_OK;
+}
+
+int nasg_batched_run(const nasg_batch* b, void* stream) {
+  if (b == nullptr || b->workspace == nullptr) return NASG_ERR_NULL;
+  if (b->n_scenes < 0 || b->n_items < 0 || b->grid < 1) return NASG_ERR_WORKSPACE;
+  if (b->n_items == 0) return NASG_OK;
+  auto* base = static_cast<unsigned char*>(b->workspace);
+  auto* hdr = reinterpret_cast<nasg::BatchHeader*>(base);
+  auto* scenes = reinterpret_cast<const nasg::BatchScene*>(base + sizeof(nasg::BatchHeader));
+  const size_t items_off =
+      align_up(sizeof(nasg::BatchHeader) + sizeof(nasg::BatchScene) * b->n_scenes, 64);
+  auto* items = reinterpret_cast<const nasg::BatchItem*>(base + items_off);
+  const hipError_t e = nasg::launch_batched(hdr, scenes, items, &hdr->counter, b->token, b->grid,
+                                            static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
 }
 

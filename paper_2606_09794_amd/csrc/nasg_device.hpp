@@ -112,8 +112,10 @@ __device__ inline double log_kappa(double h, double kap) {
 // e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
 // with q the Taylor series of (e^r - 1)/r to r^11/12!; e^B - 1 is taken from
 // r q(r) directly when n = 0 so it stays relatively accurate for small |B|.
+// B below -1400 is clamped there (e^-1400 underflows FP64 to 0 either way).
 __device__ inline void exp_em1(double B, double& eb, double& em1) {
-  const double n = fmax(rint(B * kLog2e), -2000.0);
+  B = fmax(B, -1400.0);
+  const double n = rint(B * kLog2e);
   double r = fma(-n, kLn2Hi, B);
   r = fma(-n, kLn2Lo, r);
   double q = 1.0 / 479001600.0;        // 1/12!
@@ -140,12 +142,43 @@ __device__ inline void exp_em1(double B, double& eb, double& em1) {
 
 // e^X as float for X <= 0: FP64 reduction X = n ln2 + r, then the hardware
 // base-2 exponential of the small remainder and an exact power-of-two scale.
+// X below -200 is clamped there (e^-200 underflows FP32 to 0 either way).
 __device__ inline float exp_neg(double X) {
-  const double n = fmax(rint(X * kLog2e), -400.0);
+  X = fmax(X, -200.0);
+  const double n = rint(X * kLog2e);
   double r = fma(-n, kLn2Hi, X);
   r = fma(-n, kLn2Lo, r);
   const float p = __builtin_amdgcn_exp2f(static_cast<float>(r * kLog2e));
   return ldexpf(p, static_cast<int>(n));
+}
+
+// sin(2 pi t) and cos(2 pi t) in FP64 for any t: t is reduced to the nearest
+// integer and quarter turn, leaving |r| <= pi/4 for the Taylor series
+// (sine to r^13, cosine to r^14; truncation below 1e-14).
+__device__ inline void sincos_turns(double t, double& s, double& c) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+  const double f = t - rint(t);
+  const double qd = rint(4.0 * f);
+  const double r = (f - 0.25 * qd) * kTwoPi;
+  const double z = r * r;
+  double ps = 1.0 / 6227020800.0;      // 1/13!
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  const double sr = fma(ps * z, r, r);
+  double pc = 1.0 / 87178291200.0;     // 1/14!
+  pc = fma(pc, z, -1.0 / 479001600.0);
+  pc = fma(pc, z, 1.0 / 3628800.0);
+  pc = fma(pc, z, -1.0 / 40320.0);
+  pc = fma(pc, z, 1.0 / 720.0);
+  pc = fma(pc, z, -1.0 / 24.0);
+  pc = fma(pc, z, 0.5);
+  const double cr = fma(-pc, z, 1.0);
+  const int q = static_cast<int>(qd) & 3;
+  s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+  c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
 }
 
 // ------------------------------------------------------------- normaliser
@@ -157,10 +190,12 @@ struct LobeNorm {
 };
 
 // e^{-L} S(r) and e^{-L} S'(r) with S(r) = sinh(sqrt r)/sqrt r continued to
-// r < 0 as sin(sqrt(-r))/sqrt(-r); r = L^2 - k^2. Power series for |r| <= 1,
-// otherwise the overflow-free exponential form with s - L = -k^2 / (L + s).
+// r < 0 as sin(sqrt(-r))/sqrt(-r); r = L^2 - k^2 (Section 5.1, Psi). Power
+// series for |r| <= 1, otherwise the overflow-free exponential form with
+// s - L = -k^2 / (L + s).
 __device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
   const double r = L * L - k * k;
+  double eL, unused;
   if (fabs(r) <= 1.0) {
     // 1/(2n+1)! for n = 0..13
     constexpr double c[14] = {1.0,
@@ -177,70 +212,80 @@ __device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
                               1.0 / 25852016738884976640000.0,
                               1.0 / 15511210043330985984000000.0,
                               1.0 / 10888869450418352160768000000.0};
-    double s = c[13], ds = 13.0 * c[13];
+    double sr = c[13], ds = 13.0 * c[13];
 #pragma unroll
     for (int n = 12; n >= 1; --n) {
-      s = fma(s, r, c[n]);
+      sr = fma(sr, r, c[n]);
       ds = fma(ds, r, n * c[n]);
     }
-    s = fma(s, r, c[0]);
-    const double e = exp(-L);
-    F = e * s;
-    dF = e * ds;
+    sr = fma(sr, r, c[0]);
+    exp_em1(-L, eL, unused);
+    F = eL * sr;
+    dF = eL * ds;
   } else if (r > 0.0) {
     const double s = sqrt(r);
-    const double ep = exp(-k * k / (L + s));  // e^{s - L}
-    const double em = exp(-s - L);           // e^{-s - L}
+    double ep, em;
+    exp_em1(-k * k * rcp64(L + s), ep, unused);  // e^{s - L}
+    exp_em1(-s - L, em, unused);                  // e^{-s - L}
     const double sh = 0.5 * (ep - em), ch = 0.5 * (ep + em);
-    F = sh / s;
-    dF = (s * ch - sh) / (2.0 * s * s * s);
+    const double is = rcp64(s);
+    F = sh * is;
+    dF = (s * ch - sh) * 0.5 * is * is * is;
   } else {
     const double t = sqrt(-r);
     double sn, cs;
-    sincos(t, &sn, &cs);
-    const double e = exp(-L);
-    F = e * sn / t;
-    dF = e * (sn - t * cs) / (2.0 * t * t * t);
+    sincos_turns(t * kInvTwoPi, sn, cs);
+    exp_em1(-L, eL, unused);
+    const double it = rcp64(t);
+    F = eL * sn * it;
+    dF = eL * (sn - t * cs) * 0.5 * it * it * it;
   }
 }
 
 // Normaliser of one lobe and the log-derivatives the backward pass needs.
-// mode 0: 1 / closed-form integral (phase multiplies Psi by cos zeta);
+// mode 0: 1 / closed-form integral (Section 5.1; the phase multiplies Psi by
+//         cos zeta);
 // mode 1: NASG normaliser lambda sqrt(1+a) / (2 pi (1 - e^{-2 lambda})).
 __device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, int mode) {
   const double lam = lamf, a = af;
-  const double em2l = -expm1(-2.0 * lam);       // 1 - e^{-2 lam}
+  double e2l, em1_2l;
+  exp_em1(-2.0 * lam, e2l, em1_2l);
+  const double dlam = -em1_2l;                    // 1 - e^{-2 lam}, relatively accurate
   const double sq = sqrt(1.0 + a);
-  // d/dlam ln(lam / (1 - e^{-2 lam})) = 1/lam - 2/(e^{2 lam} - 1)
-  const double dl_base = 1.0 / lam - 2.0 / expm1(2.0 * lam);
-  const double da_base = 0.5 / (1.0 + a);
+  const double idl = rcp64(dlam);
+  // d/dlam ln(lam / (1 - e^{-2 lam})) = 1/lam - 2 e^{-2 lam} / (1 - e^{-2 lam})
+  const double dl_base = rcp64(lam) - 2.0 * e2l * idl;
+  const double da_base = 0.5 * rcp64(1.0 + a);
   LobeNorm out;
   if (mode == 1) {
-    out.n = static_cast<float>(lam * sq / (2.0 * kPi * em2l));
+    out.n = static_cast<float>(lam * sq * idl * (0.5 / kPi));
     out.dl = static_cast<float>(dl_base);
     out.da = static_cast<float>(da_base);
     out.dk = 0.f;
     out.dz = 0.f;
     return out;
   }
-  const double k = kf, zeta = zf;
+  const double k = kf;
   const double L = lam * (1.0 + a);
   double F, dFs;
   exp_sinhc(L, k, F, dFs);
-  const double D = -expm1(-2.0 * L);            // 1 - e^{-2L}
-  const double psi = 2.0 * L * F / D;
+  double e2L, em1_2L;
+  exp_em1(-2.0 * L, e2L, em1_2L);
+  const double iD = rcp64(-em1_2L);               // 1 / (1 - e^{-2L})
+  const double psi = 2.0 * L * F * iD;
   const double dF_dL = -F + 2.0 * L * dFs;
-  const double dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) / D - 4.0 * L * F * exp(-2.0 * L) / (D * D);
-  const double dpsi_dk = -4.0 * L * k * dFs / D;
+  const double dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) * iD - 4.0 * L * F * e2L * iD * iD;
+  const double dpsi_dk = -4.0 * L * k * dFs * iD;
   double sz, cz;
-  sincos(zeta, &sz, &cz);
+  sincos_turns(static_cast<double>(zf) * kInvTwoPi, sz, cz);
   const double B = 1.0 + cz * psi;
+  const double iB = rcp64(B);
   // I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) * B ;  N = 1/I
-  out.n = static_cast<float>(lam * sq / (kPi * em2l * B));
-  out.dl = static_cast<float>(dl_base - cz * dpsi_dL * (1.0 + a) / B);
-  out.da = static_cast<float>(da_base - cz * dpsi_dL * lam / B);
-  out.dk = static_cast<float>(-cz * dpsi_dk / B);
-  out.dz = static_cast<float>(sz * psi / B);
+  out.n = static_cast<float>(lam * sq * idl * iB * (1.0 / kPi));
+  out.dl = static_cast<float>(dl_base - cz * dpsi_dL * (1.0 + a) * iB);
+  out.da = static_cast<float>(da_base - cz * dpsi_dL * lam * iB);
+  out.dk = static_cast<float>(-cz * dpsi_dk * iB);
+  out.dz = static_cast<float>(sz * psi * iB);
   return out;
 }
 

@@ -3,13 +3,15 @@
 //
 // Work mapping: each primitive owns P consecutive lanes of a wavefront; lane j
 // evaluates views v = v0 + j + P*t (t < VPL) of that primitive, so one
-// primitive's views never leave its lane group. For every lobe the lane loads
-// the lobe parameters (structure-of-arrays, coalesced across primitives),
-// builds the frame in FP64, and then loops over its views keeping the
-// per-view state (direction, upstream gradient, colour and direction-gradient
-// accumulators) in registers. Per-lobe gradient partial sums live in
-// registers, are summed over the lane group with DPP row operations and
-// written once per lobe - no atomics, fixed summation order.
+// primitive's views never leave its lane group. Lobes are taken P at a time:
+// lane j loads lobe lc + j (structure-of-arrays, coalesced across primitives)
+// and prepares its per-lobe constants (FP64 frame, normaliser and its
+// log-derivatives) once; the group then walks those P lobes, reading each
+// lobe's constants from the lane that prepared it (ds_bpermute), and loops over
+// its own views with the per-view state (direction, upstream gradient, colour
+// and direction-gradient accumulators) in registers. Per-lobe gradient partial
+// sums are summed over the lane group with DPP row operations and written by
+// the preparing lane - no atomics, fixed summation order.
 //
 // Numerics: the view direction, the frame axes and the dot products d.x, d.z,
 // h = 1 - d.z and 1 - (d.z)^2 = h (2 - h) are FP64 (the lobes reach
@@ -40,12 +42,38 @@
 
 namespace nasg {
 
+// Value of lane `src` of this lane's group of P (ds_bpermute; P = 1 is a no-op).
+template <int P>
+__device__ inline float group_bcast(float x, int src) {
+  if constexpr (P == 1) {
+    return x;
+  } else {
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int addr = ((lane & ~(P - 1)) + src) << 2;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+  }
+}
+
+template <int P>
+__device__ inline double group_bcast(double x, int src) {
+  if constexpr (P == 1) {
+    return x;
+  } else {
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int addr = ((lane & ~(P - 1)) + src) << 2;
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<long long>(lo) & 0xffffffffll));
+  }
+}
+
+// One primitive-lane-group's work: primitive `prim` (may be >= n for tail
+// lanes, which compute on a real primitive and write nothing), lane j of P.
 template <int P, int VPL, bool BWD, bool BF16>
-__global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
+__device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j) {
   using S = Store<BF16>;
-  const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t prim = gt / P;
-  const int j = static_cast<int>(gt & (P - 1));
   const int64_t N = a.n;
   const bool valid = prim < N;
   const int64_t i = valid ? prim : N - 1;  // tail lanes compute on a real primitive, write nothing
@@ -108,177 +136,193 @@ __global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
       }
     }
 
-    // ---- lobes
-    for (int l = 0; l < K; ++l) {
-      const int64_t li = static_cast<int64_t>(l) * N + i;
-      const float4 q = S::load4(a.quat, li);
-      const float4 sh = S::load4(a.shape, li);
-      const float w0 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 0) * N + i);
-      const float w1 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 1) * N + i);
-      const float w2 = S::load1(a.rgbw, (static_cast<int64_t>(l) * 3 + 2) * N + i);
-      const float lam = sh.x, an = sh.y, kf = sh.z, zf = sh.w;
-
+    // ---- lobes, P at a time: lane j prepares lobe lc + j, the group shares it
+    for (int lc = 0; lc < K; lc += P) {
+      const int lo = min(lc + j, K - 1);
+      const int64_t oi = static_cast<int64_t>(lo) * N + i;
+      const float4 q = S::load4(a.quat, oi);
+      const float4 sh = S::load4(a.shape, oi);
+      const float ow0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
+      const float ow1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
+      const float ow2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
       // frame: x = M_x(q)/|q|^2, z = M_z(q)/|q|^2 (homogeneous rotation of q)
       const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
       const double ww = qw * qw, xx = qx * qx, yy = qy * qy, zz = qz * qz;
-      const double is = 1.0 / (ww + xx + yy + zz);
-      const double xa0 = (ww + xx - yy - zz) * is;
-      const double xa1 = 2.0 * (qx * qy + qw * qz) * is;
-      const double xa2 = 2.0 * (qx * qz - qw * qy) * is;
-      const double za0 = 2.0 * (qx * qz + qw * qy) * is;
-      const double za1 = 2.0 * (qy * qz - qw * qx) * is;
-      const double za2 = (ww - xx - yy + zz) * is;
-      const double krev = static_cast<double>(kf) * kInvTwoPi;
-      const double zrev = static_cast<double>(zf) * kInvTwoPi;
-      const LobeNorm nm = lobe_norm(lam, an, kf, zf, a.norm);
-      const float Nn = nm.n;
-      const float two_lam = 2.f * lam;
+      const double is = rcp64(ww + xx + yy + zz);
+      const double oxa0 = (ww + xx - yy - zz) * is;
+      const double oxa1 = 2.0 * (qx * qy + qw * qz) * is;
+      const double oxa2 = 2.0 * (qx * qz - qw * qy) * is;
+      const double oza0 = 2.0 * (qx * qz + qw * qy) * is;
+      const double oza1 = 2.0 * (qy * qz - qw * qx) * is;
+      const double oza2 = (ww - xx - yy + zz) * is;
+      const double okrev = static_cast<double>(sh.z) * kInvTwoPi;
+      const double ozrev = static_cast<double>(sh.w) * kInvTwoPi;
+      const LobeNorm nm = lobe_norm(sh.x, sh.y, sh.z, sh.w, a.norm);
 
-      float acc_w0 = 0.f, acc_w1 = 0.f, acc_w2 = 0.f, acc_G = 0.f, acc_l = 0.f, acc_a = 0.f;
-      float acc_k = 0.f, acc_z = 0.f;
-      float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
-      const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
-                  xf2 = static_cast<float>(xa2);
-      const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
-                  zf2 = static_cast<float>(za2);
+      const int nsub = min(P, K - lc);
+      for (int s = 0; s < nsub; ++s) {
+        const int l = lc + s;
+        const double xa0 = group_bcast<P>(oxa0, s), xa1 = group_bcast<P>(oxa1, s),
+                     xa2 = group_bcast<P>(oxa2, s);
+        const double za0 = group_bcast<P>(oza0, s), za1 = group_bcast<P>(oza1, s),
+                     za2 = group_bcast<P>(oza2, s);
+        const double krev = group_bcast<P>(okrev, s), zrev = group_bcast<P>(ozrev, s);
+        const float lam = group_bcast<P>(sh.x, s), an = group_bcast<P>(sh.y, s);
+        const float kf = group_bcast<P>(sh.z, s);
+        const float w0 = group_bcast<P>(ow0, s), w1 = group_bcast<P>(ow1, s),
+                    w2 = group_bcast<P>(ow2, s);
+        const float Nn = group_bcast<P>(nm.n, s);
+        const float two_lam = 2.f * lam;
+        const double two_lamd = 2.0 * static_cast<double>(lam);
+        const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
+                    xf2 = static_cast<float>(xa2);
+        const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
+                    zf2 = static_cast<float>(za2);
+
+        float acc_w0 = 0.f, acc_w1 = 0.f, acc_w2 = 0.f, acc_G = 0.f, acc_l = 0.f, acc_a = 0.f;
+        float acc_k = 0.f, acc_z = 0.f;
+        float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
 
 #pragma unroll
-      for (int t = 0; t < VPL; ++t) {
-        if (!has[t]) continue;
-        const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
-        const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
-        const double hd = 1.0 - dzd;
-        const double kapd = 0.5 * (1.0 + dzd);
-        if (!(kapd > 0.0)) continue;  // d = -z: G = 0 and no gradient
-        const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
-        const float dx = static_cast<float>(dxd);
-        const float kap = static_cast<float>(kapd);
-        // carrier phase in revolutions, reduced to the nearest integer
-        // (theta = 2 pi (f + integer), |f| <= 1/2). The carrier is cos^2(pi f) and
-        // dc/dtheta = -sign(f) sin(pi|f|) cos(pi|f|); both are evaluated from the
-        // smaller of |f| and 1/2 - |f| so they stay relatively accurate at the
-        // carrier's peaks and zeros alike.
-        const double tr = fma(dxd, krev, zrev);
-        const double fr = tr - rint(tr);
-        const double fa = fabs(fr);
-        const bool near_peak = fa <= 0.25;
-        float sa, ca;
-        sincospif(static_cast<float>(near_peak ? fa : 0.5 - fa), &sa, &ca);
-        const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
-        const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
-        const float car = cos_f * cos_f;
-        // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
-        const bool pole = !(dend > 0.0);
-        const double rden = pole ? 0.0 : rcp64(dend);
-        const double Ld = log_kappa(hd, kapd);
-        const double ud = dxd * dxd * rden;        // tau / a
-        const double taud = static_cast<double>(an) * ud;
-        const double Ad = taud * Ld;               // ln E
-        double Ekd, em1d;
-        exp_em1(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
-        const float pE = exp_neg(fma(2.0 * static_cast<double>(lam), em1d, Ad));
-        const float L = static_cast<float>(Ld);
-        const float LR = pole ? -0.25f : static_cast<float>(Ld * rden);  // ln kappa / (1-(d.z)^2)
-        const float u = static_cast<float>(ud);
-        const float tau = static_cast<float>(taud);
-        const float em1 = static_cast<float>(em1d);
-        const float Npe = Nn * pE;
-        const float G = Npe * car;
-        col[t][0] = fmaf(w0, G, col[t][0]);
-        col[t][1] = fmaf(w1, G, col[t][1]);
-        col[t][2] = fmaf(w2, G, col[t][2]);
-        if constexpr (BWD) {
-          const float g0 = gr[t][0], g1 = gr[t][1], g2 = gr[t][2];
-          const float gG = fmaf(g0, w0, fmaf(g1, w1, g2 * w2));
-          acc_w0 = fmaf(g0, G, acc_w0);
-          acc_w1 = fmaf(g1, G, acc_w1);
-          acc_w2 = fmaf(g2, G, acc_w2);
-          const float qG = gG * G;
-          acc_G += qG;
-          acc_l = fmaf(qG, em1, acc_l);
-          const float Ek = 1.f + em1;
-          const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
-          acc_a = fmaf(qG * T2 * L, u, acc_a);
-          const float fsg = fr < 0.0 ? 1.f : -1.f;        // -sign(f)
-          const float Sth = fsg * sin_f * cos_f * Npe;    // N p E dc/dtheta
-          const float gS = gG * Sth;
-          acc_k = fmaf(gS, dx, acc_k);
-          acc_z += gS;
-          const float sx = fmaf(G * T2 * LR, 2.f * an * dx, Sth * kf);
-          const float inv2k = 0.5f / kap;
-          const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
-                                T2 * LR * tau * 2.f * static_cast<float>(dzd));
-          const float gsx = gG * sx, gsz = gG * sz;
-          ax0 = fmaf(gsx, df[t][0], ax0);
-          ax1 = fmaf(gsx, df[t][1], ax1);
-          ax2 = fmaf(gsx, df[t][2], ax2);
-          az0 = fmaf(gsz, df[t][0], az0);
-          az1 = fmaf(gsz, df[t][1], az1);
-          az2 = fmaf(gsz, df[t][2], az2);
-          gdir[t][0] = fmaf(gsx, xf0, fmaf(gsz, zf0, gdir[t][0]));
-          gdir[t][1] = fmaf(gsx, xf1, fmaf(gsz, zf1, gdir[t][1]));
-          gdir[t][2] = fmaf(gsx, xf2, fmaf(gsz, zf2, gdir[t][2]));
+        for (int t = 0; t < VPL; ++t) {
+          if (!has[t]) continue;
+          const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
+          const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
+          const double hd = 1.0 - dzd;
+          const double kapd = 0.5 * (1.0 + dzd);
+          if (!(kapd > 0.0)) continue;  // d = -z: G = 0 and no gradient
+          const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
+          const float dx = static_cast<float>(dxd);
+          const float kap = static_cast<float>(kapd);
+          // carrier phase in revolutions, reduced to the nearest integer
+          // (theta = 2 pi (f + integer), |f| <= 1/2). The carrier is cos^2(pi f)
+          // and dc/dtheta = -sign(f) sin(pi|f|) cos(pi|f|); both are evaluated
+          // from the smaller of |f| and 1/2 - |f| so they stay relatively
+          // accurate at the carrier's peaks and zeros alike.
+          const double tr = fma(dxd, krev, zrev);
+          const double fr = tr - rint(tr);
+          const double fa = fabs(fr);
+          const bool near_peak = fa <= 0.25;
+          float sa, ca;
+          sincospif(static_cast<float>(near_peak ? fa : 0.5 - fa), &sa, &ca);
+          const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
+          const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
+          const float car = cos_f * cos_f;
+          // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
+          const bool pole = !(dend > 0.0);
+          const double rden = pole ? 0.0 : rcp64(dend);
+          const double Ld = log_kappa(hd, kapd);
+          const double ud = dxd * dxd * rden;        // tau / a
+          const double taud = static_cast<double>(an) * ud;
+          const double Ad = taud * Ld;               // ln E
+          double Ekd, em1d;
+          exp_em1(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
+          const float pE = exp_neg(fma(two_lamd, em1d, Ad));
+          const float Npe = Nn * pE;
+          const float G = Npe * car;
+          col[t][0] = fmaf(w0, G, col[t][0]);
+          col[t][1] = fmaf(w1, G, col[t][1]);
+          col[t][2] = fmaf(w2, G, col[t][2]);
+          if constexpr (BWD) {
+            const float L = static_cast<float>(Ld);
+            const float LR = pole ? -0.25f : static_cast<float>(Ld * rden);  // ln kappa/(1-(d.z)^2)
+            const float u = static_cast<float>(ud);
+            const float tau = static_cast<float>(taud);
+            const float em1 = static_cast<float>(em1d);
+            const float g0 = gr[t][0], g1 = gr[t][1], g2 = gr[t][2];
+            const float gG = fmaf(g0, w0, fmaf(g1, w1, g2 * w2));
+            acc_w0 = fmaf(g0, G, acc_w0);
+            acc_w1 = fmaf(g1, G, acc_w1);
+            acc_w2 = fmaf(g2, G, acc_w2);
+            const float qG = gG * G;
+            acc_G += qG;
+            acc_l = fmaf(qG, em1, acc_l);
+            const float Ek = 1.f + em1;
+            const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
+            acc_a = fmaf(qG * T2 * L, u, acc_a);
+            const float fsg = fr < 0.0 ? 1.f : -1.f;          // -sign(f)
+            const float Sth = fsg * sin_f * cos_f * Npe;      // N p E dc/dtheta
+            const float gS = gG * Sth;
+            acc_k = fmaf(gS, dx, acc_k);
+            acc_z += gS;
+            const float sx = fmaf(G * T2 * LR, 2.f * an * dx, Sth * kf);
+            const float inv2k = 0.5f / kap;
+            const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
+                                  T2 * LR * tau * 2.f * static_cast<float>(dzd));
+            const float gsx = gG * sx, gsz = gG * sz;
+            ax0 = fmaf(gsx, df[t][0], ax0);
+            ax1 = fmaf(gsx, df[t][1], ax1);
+            ax2 = fmaf(gsx, df[t][2], ax2);
+            az0 = fmaf(gsz, df[t][0], az0);
+            az1 = fmaf(gsz, df[t][1], az1);
+            az2 = fmaf(gsz, df[t][2], az2);
+            gdir[t][0] = fmaf(gsx, xf0, fmaf(gsz, zf0, gdir[t][0]));
+            gdir[t][1] = fmaf(gsx, xf1, fmaf(gsz, zf1, gdir[t][1]));
+            gdir[t][2] = fmaf(gsx, xf2, fmaf(gsz, zf2, gdir[t][2]));
+          }
         }
-      }
 
-      if constexpr (BWD) {
-        acc_w0 = group_sum<P>(acc_w0);
-        acc_w1 = group_sum<P>(acc_w1);
-        acc_w2 = group_sum<P>(acc_w2);
-        acc_G = group_sum<P>(acc_G);
-        acc_l = group_sum<P>(acc_l);
-        acc_a = group_sum<P>(acc_a);
-        acc_k = group_sum<P>(acc_k);
-        acc_z = group_sum<P>(acc_z);
-        ax0 = group_sum<P>(ax0);
-        ax1 = group_sum<P>(ax1);
-        ax2 = group_sum<P>(ax2);
-        az0 = group_sum<P>(az0);
-        az1 = group_sum<P>(az1);
-        az2 = group_sum<P>(az2);
-        if (valid) {
-          // the lane group splits the three stores
-          if (a.g_shape != nullptr && j == (1 % P)) {
-            float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
-                                    fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
-            float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
-            if (acc_mode) {
-              const float4 o = *dst;
-              gs.x += o.x; gs.y += o.y; gs.z += o.z; gs.w += o.w;
+        if constexpr (BWD) {
+          acc_w0 = group_sum<P>(acc_w0);
+          acc_w1 = group_sum<P>(acc_w1);
+          acc_w2 = group_sum<P>(acc_w2);
+          acc_G = group_sum<P>(acc_G);
+          acc_l = group_sum<P>(acc_l);
+          acc_a = group_sum<P>(acc_a);
+          acc_k = group_sum<P>(acc_k);
+          acc_z = group_sum<P>(acc_z);
+          ax0 = group_sum<P>(ax0);
+          ax1 = group_sum<P>(ax1);
+          ax2 = group_sum<P>(ax2);
+          az0 = group_sum<P>(az0);
+          az1 = group_sum<P>(az1);
+          az2 = group_sum<P>(az2);
+          // the lane that prepared lobe l owns its constants and writes its gradients
+          if (valid && j == s) {
+            const int64_t li = static_cast<int64_t>(l) * N + i;
+            if (a.g_shape != nullptr) {
+              float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
+                                      fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
+              float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
+              if (acc_mode) {
+                const float4 o = *dst;
+                gs.x += o.x; gs.y += o.y; gs.z += o.z; gs.w += o.w;
+              }
+              *dst = gs;
             }
-            *dst = gs;
-          }
-          if (a.g_quat != nullptr && j == 0) {
-            // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
-            const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
-            const float fis = static_cast<float>(is);
-            const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 + zf1 * az1 + zf2 * az2);
-            float4 gq;
-            gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
-            gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
-            gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
-            gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
-            gq.x = (gq.x - rad * fw) * fis;
-            gq.y = (gq.y - rad * fx) * fis;
-            gq.z = (gq.z - rad * fy) * fis;
-            gq.w = (gq.w - rad * fz) * fis;
-            float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
-            if (acc_mode) {
-              const float4 o = *dst;
-              gq.x += o.x; gq.y += o.y; gq.z += o.z; gq.w += o.w;
+            if (a.g_quat != nullptr) {
+              // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
+              const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
+              const float fis = static_cast<float>(is);
+              const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 + zf1 * az1 +
+                                       zf2 * az2);
+              float4 gq;
+              gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
+              gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
+              gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
+              gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
+              gq.x = (gq.x - rad * fw) * fis;
+              gq.y = (gq.y - rad * fx) * fis;
+              gq.z = (gq.z - rad * fy) * fis;
+              gq.w = (gq.w - rad * fz) * fis;
+              float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
+              if (acc_mode) {
+                const float4 o = *dst;
+                gq.x += o.x; gq.y += o.y; gq.z += o.z; gq.w += o.w;
+              }
+              *dst = gq;
             }
-            *dst = gq;
-          }
-          if (a.g_rgbw != nullptr && j == (2 % P)) {
-            float* dst = a.g_rgbw + static_cast<int64_t>(l) * 3 * N + i;
-            if (acc_mode) {
-              acc_w0 += dst[0];
-              acc_w1 += dst[N];
-              acc_w2 += dst[2 * N];
+            if (a.g_rgbw != nullptr) {
+              float* dst = a.g_rgbw + static_cast<int64_t>(l) * 3 * N + i;
+              if (acc_mode) {
+                acc_w0 += dst[0];
+                acc_w1 += dst[N];
+                acc_w2 += dst[2 * N];
+              }
+              dst[0] = acc_w0;
+              dst[N] = acc_w1;
+              dst[2 * N] = acc_w2;
             }
-            dst[0] = acc_w0;
-            dst[N] = acc_w1;
-            dst[2 * N] = acc_w2;
           }
         }
       }
@@ -342,6 +386,61 @@ __global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
       }
     }
   }
+}
+
+template <int P, int VPL, bool BWD, bool BF16>
+__global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
+  const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  nasg_body<P, VPL, BWD, BF16>(a, gt / P, static_cast<int>(gt & (P - 1)));
+}
+
+// ------------------------------------------------------- persistent batch
+
+template <int P, int VPL>
+__device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int iters) {
+  constexpr int kPrimsPerPass = 256 / P;
+  for (int m = 0; m < iters; ++m) {
+    const int64_t base = start + static_cast<int64_t>(m) * kPrimsPerPass;
+    if (base >= a.n) break;  // uniform across the block
+    nasg_body<P, VPL, true, false>(a, base + threadIdx.x / P, static_cast<int>(threadIdx.x & (P - 1)));
+  }
+}
+
+__global__ void batch_reset(uint32_t* counter) { *counter = 0u; }
+
+// Pulls tiles from the queue until it is empty; every block exits when the
+// head passes n_items. A plan whose token does not match is not run.
+__global__ __launch_bounds__(256) void nasg_batched_kernel(const BatchHeader* hdr,
+                                                           const BatchScene* scenes,
+                                                           const BatchItem* items,
+                                                           uint32_t* counter, uint64_t token) {
+  __shared__ int s_item;
+  if (hdr->token != token) return;
+  const int n_items = hdr->n_items;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(counter, 1u));
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem item = items[it];
+    const BatchScene& sc = scenes[item.scene];
+    switch (sc.variant) {
+      case 0: batch_tile<1, 1>(sc.args, item.start, sc.tile_iters); break;
+      case 1: batch_tile<1, 4>(sc.args, item.start, sc.tile_iters); break;
+      default: batch_tile<4, 4>(sc.args, item.start, sc.tile_iters); break;
+    }
+  }
+}
+
+hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
+                          uint32_t* counter, uint64_t token, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(nasg_batched_kernel, dim3(grid), dim3(256), 0, s, hdr, scenes, items, counter,
+                     token);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ instantiation

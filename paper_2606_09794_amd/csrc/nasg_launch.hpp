@@ -57,6 +57,34 @@ struct ShArgs {
   X(8, 2)                       \
   X(16, 1)
 
+// Persistent multi-scene launch: device-side plan layout (in the caller's
+// workspace): BatchHeader | BatchScene[n_scenes] | BatchItem[n_items].
+struct BatchHeader {
+  uint64_t token;
+  int32_t n_items;
+  int32_t n_scenes;
+  uint32_t counter;   // work-queue head, reset by every run
+  int32_t pad[11];
+};
+static_assert(sizeof(BatchHeader) == 64, "batch header layout");
+
+struct BatchScene {
+  NasgArgs args;
+  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (1, 4), 2 = (4, 4)
+  int32_t tile_iters;
+};
+
+struct BatchItem {
+  int32_t scene;
+  int32_t pad;
+  int64_t start;       // first primitive of the tile
+};
+
+constexpr int kBatchLanes[3] = {1, 1, 4};
+
+hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
+                          uint32_t* counter, uint64_t token, int grid, hipStream_t s);
+
 hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
                        hipStream_t s);
 hipError_t launch_sh(const ShArgs& a, int lanes, int vpl, bool bwd, int block, hipStream_t s);

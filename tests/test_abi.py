@@ -119,3 +119,33 @@ def test_status_strings_and_tuning(lib):
     assert lib.nasg_get_tuning(1, 8, 16, 0, C.byref(out)) == 0
     assert (out.lanes, out.views_per_lane) == (4, 4)
     assert lib.nasg_set_tuning(9, 8, 16, 0, C.byref(t)) == -5
+
+
+def test_batched_rejects(lib):
+    sc = (L.NasgScene * 1)()
+    sc[0] = L.NasgScene(params(), views(), FAKE, L.NasgGrads(FAKE, FAKE, FAKE, FAKE, FAKE), None)
+    out = L.NasgBatch()
+    t = L.NasgBatchTuning(4, 2)
+    need = lib.nasg_batched_workspace_bytes(sc, 1, C.byref(t))
+    assert need > 64
+    plan = lambda ws=FAKE, nbytes=need, norm=0, tt=C.byref(t), o=C.byref(out): \
+        lib.nasg_batched_plan(sc, 1, norm, tt, ws, nbytes, o, None)  # noqa: E731
+    assert plan(o=None) == -1
+    assert plan(norm=4) == -5
+    assert plan(tt=C.byref(L.NasgBatchTuning(0, 2))) == -2
+    assert plan(tt=C.byref(L.NasgBatchTuning(4, 9))) == -2
+    assert plan(ws=None) == -7
+    assert plan(nbytes=need - 1) == -7
+    assert plan(ws=FAKE + 16) == -7
+    sc[0].p.dtype = 1
+    assert plan() == -4
+    sc[0].p.dtype = 0
+    sc[0].grad_rgb = None
+    assert plan() == -1
+    assert lib.nasg_batched_run(None, None) == -1
+    empty = L.NasgBatch(FAKE, 0, 0, 0, 1, 0, 0)
+    assert lib.nasg_batched_run(C.byref(empty), None) == 0      # nothing to launch
+    # the work list grows with the tile count: one tile per 4 x 256 primitives at V = 2
+    sc[0].grad_rgb = FAKE
+    sc[0].p.n = 1024 * 3 + 1
+    assert lib.nasg_batched_workspace_bytes(sc, 1, C.byref(t)) == need + 3 * 16
