@@ -4,7 +4,11 @@
 Headline workload: NASGabor K = 8, fused forward+backward, 3 M primitives x
 16 cameras in one launch (FP32 storage, EXACT normaliser), synthetic inputs
 already resident in HBM. One step = one fused launch over the whole batch.
-Prints one JSON line; see the design doc for the byte accounting.
+Prints one JSON line. Algorithmic bytes per launch: every input read once
+(K x 44 B of float32 lobe parameters + 24 B of diffuse colour and mean per
+primitive, 12 B of upstream gradient per primitive-view) and every output
+written once (12 B of colour per primitive-view, K x 44 + 24 B of float32
+gradients per primitive).
 
     python bench.py [--steps K] [--warmup W] [--n N] [--norm exact|approx]
 """
@@ -167,10 +171,14 @@ def main():
     ap.add_argument("--norm", choices=["exact", "approx"], default="exact")
     ap.add_argument("--quick", action="store_true", help="headline only (no comparisons, no CPU leg)")
     ap.add_argument("--cpu-prims", type=int, default=8192)
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection mode: a few headline launches plus a plain "
+                         "device copy of --copy-mib MiB for calibrating byte counters")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the path shards by primitive with no "
-              "exchange, so --gpus N > 1 is not run (see DESIGN.md)", file=sys.stderr)
+              "exchange, so --gpus N > 1 is not run", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -194,6 +202,20 @@ def main():
     def fused():
         P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"], means=d["means"],
                         cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
+
+    if args.profile:
+        for _ in range(args.steps):
+            fused()
+        src = torch.empty(args.copy_mib << 18, device="cuda")        # float32 elements
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": True, "fused_launches": args.steps, "n": n, "k": k, "v": v,
+                          "copy_bytes": src.numel() * 4, "copies": 3,
+                          "algorithmic_bytes_per_launch": algorithmic_bytes(n, k, v),
+                          "source_hash": kernel_source_hash()}), flush=True)
+        return
 
     ms = time_launches(fused, args.steps, args.warmup)
     evals = n * v

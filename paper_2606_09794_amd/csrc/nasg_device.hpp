@@ -74,15 +74,15 @@ constexpr double kLn2Lo = 1.4286068203094172321214581765680755e-06;
 constexpr double kLog2e = 1.442695040888963407359924681001892137;
 constexpr double kSqrtHalf = 0.707106781186547524400844362104849039;
 
-// 1/x for x > 0 normal: hardware estimate plus two Newton steps.
+// 1/x for x > 0 normal: the hardware estimate (relative error < 5e-8
+// measured on gfx950) plus one Newton step (error ~ its square, ~2e-15).
 __device__ inline double rcp64(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
+  const double y = __builtin_amdgcn_rcp(x);
   return fma(y, fma(-x, y, 1.0), y);
 }
 
 // ln(kappa) with kappa = 1 - h/2 in (0, 1]. ln m = 2 atanh(s), s = (m-1)/(m+1),
-// summed as 2 s (1 + s^2/3 + s^4/5 + ...) with |s| <= 3 - 2 sqrt 2. Near the
+// summed as 2 s (1 + s^2/3 + ... + s^12/13) with |s| <= 3 - 2 sqrt 2. Near the
 // lobe axis (kappa >= 1/sqrt 2) s = -h/(4-h) is formed from h directly, so the
 // result keeps its relative accuracy however small h is.
 __device__ inline double log_kappa(double h, double kap) {
@@ -96,9 +96,7 @@ __device__ inline double log_kappa(double h, double kap) {
   const double den = nearby ? 4.0 - h : m + 1.0;
   const double s = num * rcp64(den);
   const double z = s * s;
-  double p = 1.0 / 17.0;
-  p = fma(p, z, 1.0 / 15.0);
-  p = fma(p, z, 1.0 / 13.0);
+  double p = 1.0 / 13.0;               // truncation ~1e-12 relative
   p = fma(p, z, 1.0 / 11.0);
   p = fma(p, z, 1.0 / 9.0);
   p = fma(p, z, 1.0 / 7.0);
@@ -110,17 +108,16 @@ __device__ inline double log_kappa(double h, double kap) {
 }
 
 // e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
-// with q the Taylor series of (e^r - 1)/r to r^11/12!; e^B - 1 is taken from
-// r q(r) directly when n = 0 so it stays relatively accurate for small |B|.
-// B below -1400 is clamped there (e^-1400 underflows FP64 to 0 either way).
+// with q the Taylor series of (e^r - 1)/r to r^9/10! (truncation ~3e-13);
+// e^B - 1 is taken from r q(r) directly when n = 0 so it stays relatively
+// accurate for small |B|. B below -1400 is clamped (e^-1400 underflows FP64
+// to 0 either way).
 __device__ inline void exp_em1(double B, double& eb, double& em1) {
   B = fmax(B, -1400.0);
   const double n = rint(B * kLog2e);
   double r = fma(-n, kLn2Hi, B);
   r = fma(-n, kLn2Lo, r);
-  double q = 1.0 / 479001600.0;        // 1/12!
-  q = fma(q, r, 1.0 / 39916800.0);     // 1/11!
-  q = fma(q, r, 1.0 / 3628800.0);
+  double q = 1.0 / 3628800.0;          // 1/10!
   q = fma(q, r, 1.0 / 362880.0);
   q = fma(q, r, 1.0 / 40320.0);
   q = fma(q, r, 1.0 / 5040.0);
@@ -142,7 +139,7 @@ __device__ inline void exp_em1(double B, double& eb, double& em1) {
 
 // e^X as float for X <= 0: FP64 reduction X = n ln2 + r, then the hardware
 // base-2 exponential of the small remainder and an exact power-of-two scale.
-// X below -200 is clamped there (e^-200 underflows FP32 to 0 either way).
+// X below -200 is clamped (e^-200 underflows FP32 to 0 either way).
 __device__ inline float exp_neg(double X) {
   X = fmax(X, -200.0);
   const double n = rint(X * kLog2e);
@@ -150,6 +147,24 @@ __device__ inline float exp_neg(double X) {
   r = fma(-n, kLn2Lo, r);
   const float p = __builtin_amdgcn_exp2f(static_cast<float>(r * kLog2e));
   return ldexpf(p, static_cast<int>(n));
+}
+
+// sin(pi x) and cos(pi x) in FP32 for x in [0, 1/4]: Taylor series of sine to
+// y^9 and cosine to y^10 in y = pi x <= pi/4 (truncation below 2e-8 relative).
+__device__ inline void sincospi_quarter(float x, float& s, float& c) {
+  const float y = 3.14159265358979323846f * x;
+  const float z = y * y;
+  float ps = 1.f / 362880.f;
+  ps = fmaf(ps, z, -1.f / 5040.f);
+  ps = fmaf(ps, z, 1.f / 120.f);
+  ps = fmaf(ps, z, -1.f / 6.f);
+  s = fmaf(y * z, ps, y);
+  float pc = -1.f / 3628800.f;
+  pc = fmaf(pc, z, 1.f / 40320.f);
+  pc = fmaf(pc, z, -1.f / 720.f);
+  pc = fmaf(pc, z, 1.f / 24.f);
+  pc = fmaf(pc, z, -0.5f);
+  c = fmaf(z, pc, 1.f);
 }
 
 // sin(2 pi t) and cos(2 pi t) in FP64 for any t: t is reduced to the nearest

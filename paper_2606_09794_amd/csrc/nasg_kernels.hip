@@ -204,7 +204,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double fa = fabs(fr);
           const bool near_peak = fa <= 0.25;
           float sa, ca;
-          sincospif(static_cast<float>(near_peak ? fa : 0.5 - fa), &sa, &ca);
+          sincospi_quarter(static_cast<float>(near_peak ? fa : 0.5 - fa), sa, ca);
           const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
           const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
           const float car = cos_f * cos_f;

@@ -149,7 +149,9 @@ def test_sh3_forward_backward(lanes, vpl):
     torch.cuda.synchronize()
     ref, scale = oracle_sh(w)
     compare(rgb.cpu().numpy(), ref["rgb"], scale["rgb"], "rgb", TOL)
-    np.testing.assert_array_equal(rgb_f.cpu().numpy(), rgb.cpu().numpy())
+    # the fused kernel is a different instruction stream: equal up to rounding
+    compare(rgb_f.cpu().numpy(), ref["rgb"], scale["rgb"], "rgb (fused)", TOL)
+    compare(rgb_f.cpu().numpy(), rgb.cpu().numpy(), scale["rgb"], "rgb fused vs forward", 2 * TOL)
     compare(g["sh"].cpu().numpy(), ref["sh"], scale["sh"], "sh", TOL)
     compare(g["geom"].cpu().numpy(), ref["geom"], scale["geom"], "geom", TOL)
 
