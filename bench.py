@@ -86,30 +86,37 @@ def measured_traffic(key):
 
 # ----------------------------------------------------------------- CPU oracle
 
+_CPU_W = None   # workload shared with forked oracle workers
+
+
 def _oracle_chunk(args):
     import oracle.nasg_ref as R
-    w, norm = args
+    import workloads as W
+    lo, hi, norm = args
+    w = W.take_primitives(_CPU_W, np.arange(lo, hi))
     R.forward_backward(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, norm, means=w.means, cams=w.cams)
     return w.n * w.v
 
 
-def cpu_baseline(w_full, prims=8192, chunk=512, norm_code=0):
+def cpu_baseline(w_full, prims=1_000_000, chunk=1024, norm_code=0):
     """Time the FP64 oracle (as written) on the first `prims` primitives of the
-    workload, split over the host's cores."""
-    import workloads as W
+    workload, split over the host's cores (forked workers share the arrays)."""
+    global _CPU_W
+    _CPU_W = w_full
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    idx = np.arange(min(prims, w_full.n))
-    chunks = [(W.take_primitives(w_full, idx[i:i + chunk]), norm_code) for i in range(0, idx.size, chunk)]
+    n = min(prims, w_full.n)
+    ranges = [(i, min(i + chunk, n), norm_code) for i in range(0, n, chunk)]
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
-        pool.map(_oracle_chunk, chunks[:cores])                   # warm the workers
+        pool.map(_oracle_chunk, ranges[:cores])                   # warm the workers
         t0 = time.perf_counter()
-        evals = sum(pool.map(_oracle_chunk, chunks))
+        evals = sum(pool.map(_oracle_chunk, ranges, chunksize=1))
         dt = time.perf_counter() - t0
+    _CPU_W = None
     return {"value": evals / dt / 1e9, "unit": "G evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 NumPy oracle, fused fwd+bwd on {idx.size} of {w_full.n} primitives x "
-                      f"{w_full.v} views (K={w_full.k}), {len(chunks)} chunks over {cores} "
-                      f"processes, {dt:.1f} s wall",
+            "sample": f"FP64 NumPy oracle, fused fwd+bwd on the first {n} of {w_full.n} primitives x "
+                      f"{w_full.v} views (K={w_full.k}), {len(ranges)} chunks of {chunk} over "
+                      f"{cores} processes, {dt:.1f} s wall",
             "cpu": platform.processor() or platform.machine()}
 
 
@@ -170,7 +177,8 @@ def main():
     ap.add_argument("--views", type=int, default=16)
     ap.add_argument("--norm", choices=["exact", "approx"], default="exact")
     ap.add_argument("--quick", action="store_true", help="headline only (no comparisons, no CPU leg)")
-    ap.add_argument("--cpu-prims", type=int, default=8192)
+    ap.add_argument("--cpu-prims", type=int, default=3_000_000,
+                    help="primitives in the CPU-oracle timing sample")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a few headline launches plus a plain "
                          "device copy of --copy-mib MiB for calibrating byte counters")

@@ -78,7 +78,7 @@ def _inputs(k: int, v: int, n: int, bf16: bool, seed: int = 0):
 
 
 def tune(kernel: int, k: int, v: int, dtype: int, n: int, steps: int = 5, norm: str = "exact",
-         save: bool = True, verbose: bool = True) -> Dict:
+         save: bool = True, verbose: bool = True, cache: str = CACHE) -> Dict:
     """Time every mapping for one key and install the fastest."""
     import torch
     d = _inputs(k, v, n, dtype == L.NASG_BF16)
@@ -121,7 +121,7 @@ def tune(kernel: int, k: int, v: int, dtype: int, n: int, steps: int = 5, norm: 
     set_tuning(kernel, k, v, dtype, lanes, vpl, block)
     choice = {"lanes": lanes, "views_per_lane": vpl, "block": block, "ms": round(ms, 4), "n": n}
     if save:
-        save_entry(kernel, k, v, dtype, choice)
+        save_entry(kernel, k, v, dtype, choice, path=cache)
     assert get_tuning(kernel, k, v, dtype) == (lanes, vpl, block)
     return choice
 
@@ -134,13 +134,14 @@ def main():
     ap.add_argument("--dtype", type=int, nargs="+", default=[0])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--cache", default=CACHE, help="JSON file the choices are written to")
     args = ap.parse_args()
     for name in args.kernels.split(","):
         kern = KERNELS[name]
         for k in (args.k if kern < 2 else [0]):
             for v in args.v:
                 for dt in (args.dtype if kern < 2 else [0]):
-                    c = tune(kern, k, v, dt, args.n, args.steps)
+                    c = tune(kern, k, v, dt, args.n, args.steps, cache=args.cache)
                     print(f"{name} K={k} V={v} dtype={dt}: {c}", flush=True)
 
 

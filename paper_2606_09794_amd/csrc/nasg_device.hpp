@@ -47,9 +47,11 @@ struct Store<true> {
 // quad_perm [1,0,3,2] and [2,3,0,1] give the quad sum; row_half_mirror pairs
 // the two quads of a half-row; row_mirror pairs the two half-rows.
 
+// The neighbour's value through a DPP move with zero fill (bound_ctrl), the
+// form the compiler folds into the consuming add (v_add_f32_dpp).
 template <int CTRL>
 __device__ inline float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
 template <int P>

@@ -185,12 +185,15 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
 
 #pragma unroll
         for (int t = 0; t < VPL; ++t) {
-          if (!has[t]) continue;
-          const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
-          const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
+          // Branch-free: a view outside V, or d = -z (G = 0 and no gradient),
+          // is evaluated at d = z with finite intermediates and masked out.
+          const double dx_raw = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
+          const double dz_raw = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
+          const bool live = has[t] && (1.0 + dz_raw > 0.0);
+          const double dxd = live ? dx_raw : 0.0;
+          const double dzd = live ? dz_raw : 1.0;
           const double hd = 1.0 - dzd;
           const double kapd = 0.5 * (1.0 + dzd);
-          if (!(kapd > 0.0)) continue;  // d = -z: G = 0 and no gradient
           const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
           const float dx = static_cast<float>(dxd);
           const float kap = static_cast<float>(kapd);
@@ -218,7 +221,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           double Ekd, em1d;
           exp_em1(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
           const float pE = exp_neg(fma(two_lamd, em1d, Ad));
-          const float Npe = Nn * pE;
+          const float Npe = live ? Nn * pE : 0.f;
           const float G = Npe * car;
           col[t][0] = fmaf(w0, G, col[t][0]);
           col[t][1] = fmaf(w1, G, col[t][1]);
@@ -246,7 +249,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             acc_k = fmaf(gS, dx, acc_k);
             acc_z += gS;
             const float sx = fmaf(G * T2 * LR, 2.f * an * dx, Sth * kf);
-            const float inv2k = 0.5f / kap;
+            const float inv2k = 0.5f * __builtin_amdgcn_rcpf(kap);
             const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
                                   T2 * LR * tau * 2.f * static_cast<float>(dzd));
             const float gsx = gG * sx, gsz = gG * sz;

@@ -42,7 +42,7 @@ def _check_nasg(w, norm, tol=TOL, fused=True):
     ref, scale = oracle_nasg(w, norm)
     rep = {"rgb": compare(rgb.cpu().numpy(), ref["rgb"], scale["rgb"], "rgb", tol)}
     if fused:
-        np.testing.assert_array_equal(rgb_f.cpu().numpy(), rgb.cpu().numpy())
+        compare(rgb_f.cpu().numpy(), ref["rgb"], scale["rgb"], "rgb (fused)", tol)
     for name in ("quat", "shape", "rgbw", "c0", "geom"):
         rep[name] = compare(g[name].cpu().numpy(), ref[name], scale[name], name, tol)
     return rep
