@@ -70,9 +70,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    if it is missing or was taken on other kernel sources."""
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (non-packed issue)
+
+
+def measured_counters(key):
+    """Per-launch counter figures (calibrated HBM bytes, VALU wave instructions)
+    from the committed rocprofv3 summary, or None if missing or taken on other
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -81,7 +85,7 @@ def measured_traffic(key):
     ent = data.get(key)
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
 # ----------------------------------------------------------------- CPU oracle
@@ -231,7 +235,21 @@ def main():
     abytes = algorithmic_bytes(n, k, v)
     achieved = abytes / (ms * 1e-3) / 1e9
     log(f"fused fwd+bwd {ms:.3f} ms/step, {value:.2f} G evals/s, {achieved:.0f} GB/s algorithmic")
-    traffic = measured_traffic(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}")
+    counters = measured_counters(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}")
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes}
+    if counters is not None:
+        # VALU-issue roof: lane instructions per launch (SQ_INSTS_VALU x 64) over the live
+        # launch duration, against 256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz
+        lane_ops = counters["valu_wave_instructions_per_launch"] * 64
+        ach = lane_ops / (ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                    "unit": "T VALU lane-instructions/s", "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
+                    "traffic": counters["bytes_per_launch"],
+                    "lane_instructions_per_eval": round(lane_ops / (n * v), 1), "hbm": hbm,
+                    "kernel": "nasg_kernel (fused forward+backward)"}
+    else:
+        roofline = dict(hbm, bound="hbm", traffic=None, kernel="nasg_kernel (fused forward+backward)")
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "G evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -240,10 +258,7 @@ def main():
         "config": {"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
                                f"one launch, FP32 storage, {args.norm} normaliser",
                    "primitives": n, "lobes": k, "views": v, "norm": args.norm},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": abytes,
-                     "kernel": "nasg_kernel (fused forward+backward)"},
+        "roofline": roofline,
     }
 
     if not args.quick:

@@ -44,6 +44,8 @@ struct Store<true> {
 
 // ---------------------------------------------------------- lane-group sums
 // All-reduce over aligned groups of P consecutive lanes (P <= 16, one DPP row).
+// Call only where every lane of the wavefront is active: DPP reads an
+// inactive lane as zero.
 // quad_perm [1,0,3,2] and [2,3,0,1] give the quad sum; row_half_mirror pairs
 // the two quads of a half-row; row_mirror pairs the two half-rows.
 

@@ -10,8 +10,9 @@
 // lobe's constants from the lane that prepared it (ds_bpermute), and loops over
 // its own views with the per-view state (direction, upstream gradient, colour
 // and direction-gradient accumulators) in registers. Per-lobe gradient partial
-// sums are summed over the lane group with DPP row operations and written by
-// the preparing lane - no atomics, fixed summation order.
+// sums are summed over the lane group with DPP row operations; the preparing
+// lane keeps its lobe's sums and, once the group has walked the P lobes, every
+// lane finalises and writes its own lobe - no atomics, fixed summation order.
 //
 // Numerics: the view direction, the frame axes and the dot products d.x, d.z,
 // h = 1 - d.z and 1 - (d.z)^2 = h (2 - h) are FP64 (the lobes reach
@@ -159,9 +160,12 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       const double ozrev = static_cast<double>(sh.w) * kInvTwoPi;
       const LobeNorm nm = lobe_norm(sh.x, sh.y, sh.z, sh.w, a.norm);
 
+      // reduced gradient sums of the lobe this lane prepared
+      float k_w0 = 0.f, k_w1 = 0.f, k_w2 = 0.f, k_G = 0.f, k_l = 0.f, k_a = 0.f, k_k = 0.f,
+            k_z = 0.f, k_x0 = 0.f, k_x1 = 0.f, k_x2 = 0.f, k_z0 = 0.f, k_z1 = 0.f, k_z2 = 0.f;
+
       const int nsub = min(P, K - lc);
       for (int s = 0; s < nsub; ++s) {
-        const int l = lc + s;
         const double xa0 = group_bcast<P>(oxa0, s), xa1 = group_bcast<P>(oxa1, s),
                      xa2 = group_bcast<P>(oxa2, s);
         const double za0 = group_bcast<P>(oza0, s), za1 = group_bcast<P>(oza1, s),
@@ -266,66 +270,83 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         }
 
         if constexpr (BWD) {
-          acc_w0 = group_sum<P>(acc_w0);
-          acc_w1 = group_sum<P>(acc_w1);
-          acc_w2 = group_sum<P>(acc_w2);
-          acc_G = group_sum<P>(acc_G);
-          acc_l = group_sum<P>(acc_l);
-          acc_a = group_sum<P>(acc_a);
-          acc_k = group_sum<P>(acc_k);
-          acc_z = group_sum<P>(acc_z);
-          ax0 = group_sum<P>(ax0);
-          ax1 = group_sum<P>(ax1);
-          ax2 = group_sum<P>(ax2);
-          az0 = group_sum<P>(az0);
-          az1 = group_sum<P>(az1);
-          az2 = group_sum<P>(az2);
-          // the lane that prepared lobe l owns its constants and writes its gradients
-          if (valid && j == s) {
-            const int64_t li = static_cast<int64_t>(l) * N + i;
-            if (a.g_shape != nullptr) {
-              float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
-                                      fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
-              float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
-              if (acc_mode) {
-                const float4 o = *dst;
-                gs.x += o.x; gs.y += o.y; gs.z += o.z; gs.w += o.w;
-              }
-              *dst = gs;
+          // group sums (computed by every lane: DPP needs all lanes active);
+          // the lane that prepared this lobe keeps them
+          const bool mine = (j == s);
+#define NASG_KEEP(dst, v)                  \
+  {                                        \
+    const float sum_ = group_sum<P>(v);    \
+    dst = mine ? sum_ : dst;               \
+  }
+          NASG_KEEP(k_w0, acc_w0);
+          NASG_KEEP(k_w1, acc_w1);
+          NASG_KEEP(k_w2, acc_w2);
+          NASG_KEEP(k_G, acc_G);
+          NASG_KEEP(k_l, acc_l);
+          NASG_KEEP(k_a, acc_a);
+          NASG_KEEP(k_k, acc_k);
+          NASG_KEEP(k_z, acc_z);
+          NASG_KEEP(k_x0, ax0);
+          NASG_KEEP(k_x1, ax1);
+          NASG_KEEP(k_x2, ax2);
+          NASG_KEEP(k_z0, az0);
+          NASG_KEEP(k_z1, az1);
+          NASG_KEEP(k_z2, az2);
+#undef NASG_KEEP
+        }
+      }
+
+      // every lane finalises the lobe it prepared (all lanes at once)
+      if constexpr (BWD) {
+        if (valid && lc + j < K) {
+          const int64_t li = static_cast<int64_t>(lc + j) * N + i;
+          if (a.g_shape != nullptr) {
+            float4 gs = make_float4(fmaf(nm.dl, k_G, 2.f * k_l), fmaf(nm.da, k_G, k_a),
+                                    fmaf(nm.dk, k_G, k_k), fmaf(nm.dz, k_G, k_z));
+            float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
+            if (acc_mode) {
+              const float4 o = *dst;
+              gs.x += o.x; gs.y += o.y; gs.z += o.z; gs.w += o.w;
             }
-            if (a.g_quat != nullptr) {
-              // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
-              const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
-              const float fis = static_cast<float>(is);
-              const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 + zf1 * az1 +
-                                       zf2 * az2);
-              float4 gq;
-              gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
-              gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
-              gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
-              gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
-              gq.x = (gq.x - rad * fw) * fis;
-              gq.y = (gq.y - rad * fx) * fis;
-              gq.z = (gq.z - rad * fy) * fis;
-              gq.w = (gq.w - rad * fz) * fis;
-              float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
-              if (acc_mode) {
-                const float4 o = *dst;
-                gq.x += o.x; gq.y += o.y; gq.z += o.z; gq.w += o.w;
-              }
-              *dst = gq;
+            *dst = gs;
+          }
+          if (a.g_quat != nullptr) {
+            // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
+            const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
+            const float fis = static_cast<float>(is);
+            const float ox0 = static_cast<float>(oxa0), ox1 = static_cast<float>(oxa1),
+                        ox2 = static_cast<float>(oxa2);
+            const float oz0 = static_cast<float>(oza0), oz1 = static_cast<float>(oza1),
+                        oz2 = static_cast<float>(oza2);
+            const float rad = 2.f * (ox0 * k_x0 + ox1 * k_x1 + ox2 * k_x2 + oz0 * k_z0 +
+                                     oz1 * k_z1 + oz2 * k_z2);
+            float4 gq;
+            gq.x = 2.f * (fw * k_x0 + fz * k_x1 - fy * k_x2 + fy * k_z0 - fx * k_z1 + fw * k_z2);
+            gq.y = 2.f * (fx * k_x0 + fy * k_x1 + fz * k_x2 + fz * k_z0 - fw * k_z1 - fx * k_z2);
+            gq.z = 2.f * (-fy * k_x0 + fx * k_x1 - fw * k_x2 + fw * k_z0 + fz * k_z1 - fy * k_z2);
+            gq.w = 2.f * (-fz * k_x0 + fw * k_x1 + fx * k_x2 + fx * k_z0 + fy * k_z1 + fz * k_z2);
+            gq.x = (gq.x - rad * fw) * fis;
+            gq.y = (gq.y - rad * fx) * fis;
+            gq.z = (gq.z - rad * fy) * fis;
+            gq.w = (gq.w - rad * fz) * fis;
+            float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
+            if (acc_mode) {
+              const float4 o = *dst;
+              gq.x += o.x; gq.y += o.y; gq.z += o.z; gq.w += o.w;
             }
-            if (a.g_rgbw != nullptr) {
-              float* dst = a.g_rgbw + static_cast<int64_t>(l) * 3 * N + i;
-              if (acc_mode) {
-                acc_w0 += dst[0];
-                acc_w1 += dst[N];
-                acc_w2 += dst[2 * N];
-              }
-              dst[0] = acc_w0;
-              dst[N] = acc_w1;
-              dst[2 * N] = acc_w2;
+            *dst = gq;
+          }
+          if (a.g_rgbw != nullptr) {
+            float* dst = a.g_rgbw + static_cast<int64_t>(lc + j) * 3 * N + i;
+            float r0 = k_w0, r1 = k_w1, r2 = k_w2;
+            if (acc_mode) {
+              r0 += dst[0];
+              r1 += dst[N];
+              r2 += dst[2 * N];
             }
+            dst[0] = r0;
+            dst[N] = r1;
+            dst[2 * N] = r2;
           }
         }
       }
