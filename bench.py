@@ -172,6 +172,162 @@ def sampled_parity(w, d, g, rgb, norm, n_sample=512, seed=0):
     return {k: M.summarize(M.scaled_error(got[k], ref[k], scale[k]))["max"] for k in got}
 
 
+def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
+    """Max scaled error of device results `got` (full tensors) on sampled primitives,
+    against the oracle on the stored values (or, with orig=True, on the float32 values
+    before bf16 rounding: the quantisation cost)."""
+    import workloads as W
+    from oracle import metrics as M
+    from oracle import nasg_ref as R
+    idx = np.sort(np.random.default_rng(seed).choice(w.n, size=min(n_sample, w.n), replace=False))
+    sub = W.take_primitives(w, idx)
+    src = sub.orig if orig else {"quat": sub.quat, "shape": sub.shape, "rgbw": sub.rgbw}
+    ref, scale = R.forward_backward(src["quat"], src["shape"], src["rgbw"], sub.c0, sub.grad_rgb,
+                                    R.NORM_EXACT if norm == "exact" else R.NORM_APPROX,
+                                    means=sub.means, cams=sub.cams)
+    ref["geom"], scale["geom"] = ref.pop("means"), scale.pop("means")
+    sel = {"rgb": lambda t: t[:, idx], "quat": lambda t: t[:, idx], "shape": lambda t: t[:, idx],
+           "rgbw": lambda t: t[:, :, idx], "c0": lambda t: t[idx], "geom": lambda t: t[idx]}
+    out = {}
+    for k, f in sel.items():
+        e = M.scaled_error(f(got[k]).cpu().numpy(), ref[k], scale[k])
+        out[k] = {"max": float(e.max()), "p99": float(np.percentile(e, 99)),
+                  "frac_within_2e-2": float((e <= 2e-2).mean())} if orig else float(e.max())
+    return out
+
+
+def bench_other(args, log):
+    """Workloads other than the headline: single camera, bf16 K=16, uneven batch."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    res = {"metric": METRIC, "unit": "G evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic"}
+    if args.workload == "single-camera":
+        w = W.config1(n=args.n)
+        d = upload(w)
+        n, k, v = w.n, w.k, w.v
+        g = P.nasg_grad_buffers(k, n, "cuda")
+        rgb = torch.empty((v, n, 3), device="cuda")
+        fn = lambda: P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],  # noqa: E731
+                                     means=d["means"], cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
+        ms = time_launches(fn, args.steps, args.warmup)
+        ab = algorithmic_bytes(n, k, v)
+        gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
+        msh = time_launches(lambda: P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"],
+                                                   grads=gsh, rgb_out=rgb), args.steps, args.warmup)
+        fn()
+        torch.cuda.synchronize()
+        res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
+                   config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x 1 camera, FP32, "
+                                       f"{args.norm} normaliser", "primitives": n, "lobes": k, "views": v},
+                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   compare={"sh3_fused": {"ms": round(msh, 4), "G_evals_s": round(n * v / msh / 1e6, 4),
+                                          "hbm_frac": round(sh_bytes(n, v) / msh / 1e6 / HBM_PEAK_GBS, 4)}},
+                   parity_sampled_max_scaled_error=_sampled(w, dict(g, rgb=rgb), args.norm))
+    elif args.workload == "bf16-k16":
+        w = W.config3(n=args.n)
+        log(f"generated N={w.n} K={w.k} V={w.v} bf16")
+        d = upload(w)
+        n, k, v = w.n, w.k, w.v
+        g = P.nasg_grad_buffers(k, n, "cuda")
+        rgb = torch.empty((v, n, 3), device="cuda")
+        fn = lambda dd: P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],  # noqa: E731
+                                        means=dd["means"], cams=dd["cams"], norm=args.norm, grads=g,
+                                        rgb_out=rgb)
+        ms = time_launches(lambda: fn(d), args.steps, args.warmup)
+        fn(d)
+        torch.cuda.synchronize()
+        par = _sampled(w, dict(g, rgb=rgb), args.norm)
+        qcost = _sampled(w, dict(g, rgb=rgb), args.norm, orig=True)
+        d32 = dict(d, quat=d["quat"].float(), shape=d["shape"].float(), rgbw=d["rgbw"].float())
+        ms32 = time_launches(lambda: fn(d32), args.steps, args.warmup)
+        ab = algorithmic_bytes(n, k, v, lobe_bytes=LOBE_BYTES_BF16)
+        ab32 = algorithmic_bytes(n, k, v)
+        res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32 (bf16 storage)",
+                   config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
+                                       f"lobe parameters stored in bf16, {args.norm} normaliser",
+                           "primitives": n, "lobes": k, "views": v},
+                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   compare={"fp32_storage_same_values": {"ms": round(ms32, 4),
+                                                         "G_evals_s": round(n * v / ms32 / 1e6, 4),
+                                                         "algorithmic_bytes_per_launch": ab32}},
+                   parity_sampled_max_scaled_error=par,
+                   bf16_quantisation_cost_vs_fp32_values=qcost)
+    elif args.workload == "uneven-batch":
+        t0 = time.perf_counter()
+        scenes = W.config4()
+        log(f"generated {len(scenes)} scenes, {sum(s.workload.n for s in scenes)} primitives in "
+            f"{time.perf_counter() - t0:.1f}s")
+        dev = []
+        for sc in scenes:
+            w = sc.workload
+            dd = upload(w)
+            dd["grads"] = P.nasg_grad_buffers(w.k, w.n, "cuda")
+            dd["rgb"] = torch.empty((w.v, w.n, 3), device="cuda")
+            dev.append(dd)
+        evals = sum(sc.workload.n * sc.workload.v for sc in scenes)
+        ab = sum(algorithmic_bytes(sc.workload.n, sc.workload.k, sc.workload.v) for sc in scenes)
+        # the project's tuner: sweep tile size and persistent blocks per CU
+        sweep = []
+        for ti in (1, 2, 4, 8, 16):
+            for bpc in (1, 2, 4):
+                plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=ti, blocks_per_cu=bpc)
+                m = time_launches(plan.run, 3, 1)
+                sweep.append((m, ti, bpc))
+        m_best, ti, bpc = min(sweep)
+        plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=ti, blocks_per_cu=bpc)
+        ms = time_launches(plan.run, args.steps, args.warmup)
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            plan.run()
+        ms_graph = time_launches(graph.replay, args.steps, args.warmup)
+
+        def per_scene():
+            for dd in dev:
+                P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],
+                                means=dd["means"], cams=dd["cams"], norm=args.norm, grads=dd["grads"],
+                                rgb_out=dd["rgb"])
+        ms_sep = time_launches(per_scene, max(3, args.steps // 2), 1)
+        plan.run()
+        torch.cuda.synchronize()
+        worst = {}
+        for sc, dd in zip(scenes[::4], dev[::4]):
+            e = _sampled(sc.workload, dict(dd["grads"], rgb=dd["rgb"]), args.norm, n_sample=64)
+            for kk, vv in e.items():
+                worst[kk] = max(worst.get(kk, 0.0), vv)
+        res.update(value=round(evals / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
+                   config={"workload": f"{len(scenes)} scenes (N log-uniform in [5e4, 2e6], K in {{4,8,16}}, "
+                                       f"V in {{1,4,16}}), one persistent fused fwd+bwd launch, "
+                                       f"{args.norm} normaliser", "scenes": len(scenes),
+                           "primitives": sum(s.workload.n for s in scenes), "evals": evals,
+                           "tile_iters": ti, "blocks_per_cu": bpc, "work_items": plan.n_items},
+                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   compare={"graph_replay": {"ms": round(ms_graph, 4),
+                                             "G_evals_s": round(evals / ms_graph / 1e6, 4)},
+                            "per_scene_launches": {"ms": round(ms_sep, 4),
+                                                   "G_evals_s": round(evals / ms_sep / 1e6, 4)},
+                            "tuner_sweep_ms": {f"tile{t_}_bpc{b_}": round(m_, 4) for m_, t_, b_ in sweep}},
+                   parity_sampled_max_scaled_error=worst)
+    else:
+        raise SystemExit(f"unknown workload {args.workload}")
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +343,11 @@ def main():
                     help="counter-collection mode: a few headline launches plus a plain "
                          "device copy of --copy-mib MiB for calibrating byte counters")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "single-camera", "bf16-k16", "uneven-batch"],
+                    help="headline: K=8, 3 M primitives x 16 cameras; single-camera: K=8, 1 M x 1; "
+                         "bf16-k16: K=16, 6 M x 8, bf16 storage; uneven-batch: 32 scenes in one "
+                         "persistent launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the path shards by primitive with no "
@@ -203,6 +364,11 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     autotune.load_cache()
+    if args.workload != "headline":
+        if args.n == 3_000_000:
+            args.n = {"single-camera": 1 << 20, "bf16-k16": 6_000_000}.get(args.workload, args.n)
+        bench_other(args, log)
+        return
     t0 = time.perf_counter()
     w = W.config2(n=args.n, v=args.views)
     log(f"generated N={w.n} K={w.k} V={w.v} in {time.perf_counter() - t0:.1f}s")

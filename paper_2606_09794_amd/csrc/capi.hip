@@ -43,18 +43,15 @@ bool supported(int lanes, int vpl) {
 
 bool block_ok(int b) { return b == 64 || b == 128 || b == 256; }
 
-// Built-in choice: a primitive's views are spread over up to 16 lanes with up
-// to 4 views per lane, so per-lobe work is shared by at most 4 views and the
-// lane-group reductions stay inside one DPP row.
+// Built-in choice when no tuning entry exists (measured on MI355X): up to two
+// views per lane, so per-view state stays within the registers of two waves
+// per SIMD, and the lane group (<= one DPP row) covers up to 16 views.
 nasg_tuning heuristic(int32_t v) {
-  nasg_tuning t{1, 1, 256};
-  if (v <= 1) t = {1, 1, 256};
-  else if (v == 2) t = {1, 2, 256};
-  else if (v <= 4) t = {1, 4, 256};
-  else if (v <= 8) t = {2, 4, 256};
-  else if (v <= 16) t = {4, 4, 256};
-  else t = {8, 2, 256};
-  return t;
+  if (v <= 1) return {1, 1, 256};
+  if (v == 2) return {1, 2, 256};
+  if (v <= 4) return {2, 2, 256};
+  if (v <= 8) return {4, 2, 256};
+  return {8, 2, 256};
 }
 
 nasg_tuning choose(int32_t kernel, int32_t k, int32_t v, int32_t dtype) {

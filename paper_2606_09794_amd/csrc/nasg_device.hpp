@@ -73,6 +73,15 @@ __device__ inline float group_sum(float x) {
 // fused multiply-adds each (FP64 FMA issues at the non-packed FP32 rate on
 // CDNA4), relative error ~1e-13, inputs restricted to the ranges that occur.
 
+// a * b + c as a three-address v_fma_f64. Used in the once-per-lobe code,
+// where the compiler otherwise picks the two-address form with a hoisted
+// coefficient as the accumulator and copies it before every step.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 constexpr double kLn2Hi = 0.693145751953125;               // 2^-11 multiple
 constexpr double kLn2Lo = 1.4286068203094172321214581765680755e-06;
 constexpr double kLog2e = 1.442695040888963407359924681001892137;
@@ -85,60 +94,65 @@ __device__ inline double rcp64(double x) {
   return fma(y, fma(-x, y, 1.0), y);
 }
 
-// ln(kappa) with kappa = 1 - h/2 in (0, 1]. ln m = 2 atanh(s), s = (m-1)/(m+1),
-// summed as 2 s (1 + s^2/3 + ... + s^12/13) with |s| <= 3 - 2 sqrt 2. Near the
-// lobe axis (kappa >= 1/sqrt 2) s = -h/(4-h) is formed from h directly, so the
+// 1/sqrt(x) and sqrt(x) for x > 0 normal: the hardware estimate and one
+// Newton step, y1 = y + y (1 - x y^2)/2 (relative error ~ 1.5 times the
+// square of the estimate's).
+__device__ inline double rsqrt64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ inline double sqrt64(double x) { return x * rsqrt64(x); }
+
+// ln(kappa) with kappa = 1 - h/2 in (0, 1]: kappa = m 2^e with m in
+// [1/sqrt 2, sqrt 2), ln m = 2 atanh(s), s = (m-1)/(m+1), summed as
+// 2 s (1 + s^2/3 + ... + s^12/13) with |s| <= 3 - 2 sqrt 2 (truncation
+// ~1e-12 relative). When e = 0, m - 1 = -h/2 is taken from h itself, so the
 // result keeps its relative accuracy however small h is.
 __device__ inline double log_kappa(double h, double kap) {
-  const bool nearby = h <= 2.0 - 2.0 * kSqrtHalf;
   int e;
   double m = frexp(kap, &e);
   const bool low = m < kSqrtHalf;
   m = low ? 2.0 * m : m;
   e = low ? e - 1 : e;
-  const double num = nearby ? -h : m - 1.0;
-  const double den = nearby ? 4.0 - h : m + 1.0;
-  const double s = num * rcp64(den);
+  const double num = (e == 0) ? -0.5 * h : m - 1.0;
+  const double s = num * rcp64(m + 1.0);
   const double z = s * s;
-  double p = 1.0 / 13.0;               // truncation ~1e-12 relative
+  double p = 1.0 / 13.0;
   p = fma(p, z, 1.0 / 11.0);
   p = fma(p, z, 1.0 / 9.0);
   p = fma(p, z, 1.0 / 7.0);
   p = fma(p, z, 1.0 / 5.0);
   p = fma(p, z, 1.0 / 3.0);
   p = fma(p, z, 1.0);
-  const double ef = nearby ? 0.0 : static_cast<double>(e);
+  const double ef = static_cast<double>(e);
   return fma(ef, kLn2Hi, fma(ef, kLn2Lo, 2.0 * s * p));
 }
 
 // e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
-// with q the Taylor series of (e^r - 1)/r to r^9/10! (truncation ~3e-13);
-// e^B - 1 is taken from r q(r) directly when n = 0 so it stays relatively
-// accurate for small |B|. B below -1400 is clamped (e^-1400 underflows FP64
-// to 0 either way).
+// with q the Taylor series of (e^r - 1)/r to r^9/10! (truncation ~3e-13).
+// e^B - 1 is formed as e^B - 1, an absolute error of ~1e-16, which is all its
+// uses need (it enters 2 lam (E kappa - 1) with lam <= ~1e3). B below -1400
+// is clamped (e^-1400 underflows FP64 to 0 either way).
+template <bool THREE_ADDR = false>
 __device__ inline void exp_em1(double B, double& eb, double& em1) {
+  auto mad = [](double x, double y, double z) { return THREE_ADDR ? fma3(x, y, z) : fma(x, y, z); };
   B = fmax(B, -1400.0);
   const double n = rint(B * kLog2e);
   double r = fma(-n, kLn2Hi, B);
   r = fma(-n, kLn2Lo, r);
   double q = 1.0 / 3628800.0;          // 1/10!
-  q = fma(q, r, 1.0 / 362880.0);
-  q = fma(q, r, 1.0 / 40320.0);
-  q = fma(q, r, 1.0 / 5040.0);
-  q = fma(q, r, 1.0 / 720.0);
-  q = fma(q, r, 1.0 / 120.0);
-  q = fma(q, r, 1.0 / 24.0);
-  q = fma(q, r, 1.0 / 6.0);
-  q = fma(q, r, 0.5);
+  q = mad(q, r, 1.0 / 362880.0);
+  q = mad(q, r, 1.0 / 40320.0);
+  q = mad(q, r, 1.0 / 5040.0);
+  q = mad(q, r, 1.0 / 720.0);
+  q = mad(q, r, 1.0 / 120.0);
+  q = mad(q, r, 1.0 / 24.0);
+  q = mad(q, r, 1.0 / 6.0);
+  q = mad(q, r, 0.5);
   q = fma(q, r, 1.0);
-  const double e1 = r * q;
-  if (n == 0.0) {
-    em1 = e1;
-    eb = 1.0 + e1;
-  } else {
-    eb = ldexp(1.0 + e1, static_cast<int>(n));
-    em1 = eb - 1.0;
-  }
+  eb = ldexp(fma(r, q, 1.0), static_cast<int>(n));
+  em1 = eb - 1.0;
 }
 
 // e^X as float for X <= 0: FP64 reduction X = n ln2 + r, then the hardware
@@ -181,19 +195,19 @@ __device__ inline void sincos_turns(double t, double& s, double& c) {
   const double r = (f - 0.25 * qd) * kTwoPi;
   const double z = r * r;
   double ps = 1.0 / 6227020800.0;      // 1/13!
-  ps = fma(ps, z, -1.0 / 39916800.0);
-  ps = fma(ps, z, 1.0 / 362880.0);
-  ps = fma(ps, z, -1.0 / 5040.0);
-  ps = fma(ps, z, 1.0 / 120.0);
-  ps = fma(ps, z, -1.0 / 6.0);
+  ps = fma3(ps, z, -1.0 / 39916800.0);
+  ps = fma3(ps, z, 1.0 / 362880.0);
+  ps = fma3(ps, z, -1.0 / 5040.0);
+  ps = fma3(ps, z, 1.0 / 120.0);
+  ps = fma3(ps, z, -1.0 / 6.0);
   const double sr = fma(ps * z, r, r);
   double pc = 1.0 / 87178291200.0;     // 1/14!
-  pc = fma(pc, z, -1.0 / 479001600.0);
-  pc = fma(pc, z, 1.0 / 3628800.0);
-  pc = fma(pc, z, -1.0 / 40320.0);
-  pc = fma(pc, z, 1.0 / 720.0);
-  pc = fma(pc, z, -1.0 / 24.0);
-  pc = fma(pc, z, 0.5);
+  pc = fma3(pc, z, -1.0 / 479001600.0);
+  pc = fma3(pc, z, 1.0 / 3628800.0);
+  pc = fma3(pc, z, -1.0 / 40320.0);
+  pc = fma3(pc, z, 1.0 / 720.0);
+  pc = fma3(pc, z, -1.0 / 24.0);
+  pc = fma3(pc, z, 0.5);
   const double cr = fma(-pc, z, 1.0);
   const int q = static_cast<int>(qd) & 3;
   s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
@@ -234,30 +248,34 @@ __device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
     double sr = c[13], ds = 13.0 * c[13];
 #pragma unroll
     for (int n = 12; n >= 1; --n) {
-      sr = fma(sr, r, c[n]);
-      ds = fma(ds, r, n * c[n]);
+      sr = fma3(sr, r, c[n]);
+      ds = fma3(ds, r, n * c[n]);
     }
     sr = fma(sr, r, c[0]);
-    exp_em1(-L, eL, unused);
+    exp_em1<true>(-L, eL, unused);
     F = eL * sr;
     dF = eL * ds;
-  } else if (r > 0.0) {
-    const double s = sqrt(r);
-    double ep, em;
-    exp_em1(-k * k * rcp64(L + s), ep, unused);  // e^{s - L}
-    exp_em1(-s - L, em, unused);                  // e^{-s - L}
-    const double sh = 0.5 * (ep - em), ch = 0.5 * (ep + em);
-    const double is = rcp64(s);
-    F = sh * is;
-    dF = (s * ch - sh) * 0.5 * is * is * is;
   } else {
-    const double t = sqrt(-r);
-    double sn, cs;
-    sincos_turns(t * kInvTwoPi, sn, cs);
-    exp_em1(-L, eL, unused);
-    const double it = rcp64(t);
-    F = eL * sn * it;
-    dF = eL * (sn - t * cs) * 0.5 * it * it * it;
+    // r > 1: sinh(a)/a with e^{-L} sinh(a) = (e^{a-L} - e^{-a-L})/2, a - L = -k^2/(L+a);
+    // r < -1: sin(a)/a. The square root, its reciprocal and the first exponential
+    // (e^{a-L} or e^{-L}) are shared by both cases.
+    const double a = sqrt64(fabs(r));
+    const double ia = rcp64(a);
+    const bool hyp = r > 0.0;
+    double ex;
+    exp_em1<true>(hyp ? -k * k * rcp64(L + a) : -L, ex, unused);
+    if (hyp) {
+      double em;
+      exp_em1<true>(-a - L, em, unused);
+      const double sh = 0.5 * (ex - em), ch = 0.5 * (ex + em);
+      F = sh * ia;
+      dF = (a * ch - sh) * 0.5 * ia * ia * ia;
+    } else {
+      double sn, cs;
+      sincos_turns(a * kInvTwoPi, sn, cs);
+      F = ex * sn * ia;
+      dF = ex * (sn - a * cs) * 0.5 * ia * ia * ia;
+    }
   }
 }
 
@@ -268,9 +286,9 @@ __device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
 __device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, int mode) {
   const double lam = lamf, a = af;
   double e2l, em1_2l;
-  exp_em1(-2.0 * lam, e2l, em1_2l);
+  exp_em1<true>(-2.0 * lam, e2l, em1_2l);
   const double dlam = -em1_2l;                    // 1 - e^{-2 lam}, relatively accurate
-  const double sq = sqrt(1.0 + a);
+  const double sq = sqrt64(1.0 + a);
   const double idl = rcp64(dlam);
   // d/dlam ln(lam / (1 - e^{-2 lam})) = 1/lam - 2 e^{-2 lam} / (1 - e^{-2 lam})
   const double dl_base = rcp64(lam) - 2.0 * e2l * idl;
@@ -289,7 +307,7 @@ __device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, i
   double F, dFs;
   exp_sinhc(L, k, F, dFs);
   double e2L, em1_2L;
-  exp_em1(-2.0 * L, e2L, em1_2L);
+  exp_em1<true>(-2.0 * L, e2L, em1_2L);
   const double iD = rcp64(-em1_2L);               // 1 / (1 - e^{-2L})
   const double psi = 2.0 * L * F * iD;
   const double dF_dL = -F + 2.0 * L * dFs;

@@ -112,8 +112,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         e1 -= static_cast<double>(a.cams[3 * vc + 1]);
         e2 -= static_cast<double>(a.cams[3 * vc + 2]);
       }
-      const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
-      const double ri = 1.0 / sqrt(r2);
+      const double ri = rsqrt64(e0 * e0 + e1 * e1 + e2 * e2);
       dd[t][0] = e0 * ri;
       dd[t][1] = e1 * ri;
       dd[t][2] = e2 * ri;
@@ -189,18 +188,18 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
 
 #pragma unroll
         for (int t = 0; t < VPL; ++t) {
-          // Branch-free: a view outside V, or d = -z (G = 0 and no gradient),
-          // is evaluated at d = z with finite intermediates and masked out.
-          const double dx_raw = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
-          const double dz_raw = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
-          const bool live = has[t] && (1.0 + dz_raw > 0.0);
-          const double dxd = live ? dx_raw : 0.0;
-          const double dzd = live ? dz_raw : 1.0;
+          // Branch-free. A view slot beyond V carries a real direction and a zero
+          // upstream gradient, so it adds nothing but its (unwritten) colour; at
+          // d = -z (kappa = 0) G and every gradient are forced to 0 and kappa is
+          // kept away from 0 where it is inverted.
+          const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
+          const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
           const double hd = 1.0 - dzd;
           const double kapd = 0.5 * (1.0 + dzd);
+          const bool live = kapd > 0.0;
           const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
           const float dx = static_cast<float>(dxd);
-          const float kap = static_cast<float>(kapd);
+          const float kap = fmaxf(static_cast<float>(kapd), 1e-30f);
           // carrier phase in revolutions, reduced to the nearest integer
           // (theta = 2 pi (f + integer), |f| <= 1/2). The carrier is cos^2(pi f)
           // and dc/dtheta = -sign(f) sin(pi|f|) cos(pi|f|); both are evaluated
@@ -211,14 +210,14 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double fa = fabs(fr);
           const bool near_peak = fa <= 0.25;
           float sa, ca;
-          sincospi_quarter(static_cast<float>(near_peak ? fa : 0.5 - fa), sa, ca);
+          sincospi_quarter(static_cast<float>(0.25 - fabs(fa - 0.25)), sa, ca);  // min(|f|, 1/2-|f|)
           const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
           const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
           const float car = cos_f * cos_f;
           // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
           const bool pole = !(dend > 0.0);
           const double rden = pole ? 0.0 : rcp64(dend);
-          const double Ld = log_kappa(hd, kapd);
+          const double Ld = log_kappa(hd, fmax(kapd, 1e-300));
           const double ud = dxd * dxd * rden;        // tau / a
           const double taud = static_cast<double>(an) * ud;
           const double Ad = taud * Ld;               // ln E
@@ -434,7 +433,10 @@ __global__ void batch_reset(uint32_t* counter) { *counter = 0u; }
 
 // Pulls tiles from the queue until it is empty; every block exits when the
 // head passes n_items. A plan whose token does not match is not run.
-__global__ __launch_bounds__(256) void nasg_batched_kernel(const BatchHeader* hdr,
+// Two waves per SIMD: the three inlined lane mappings would otherwise need
+// more registers than that occupancy allows.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void nasg_batched_kernel(const BatchHeader* hdr,
                                                            const BatchScene* scenes,
                                                            const BatchItem* items,
                                                            uint32_t* counter, uint64_t token) {
@@ -451,8 +453,8 @@ __global__ __launch_bounds__(256) void nasg_batched_kernel(const BatchHeader* hd
     const BatchScene& sc = scenes[item.scene];
     switch (sc.variant) {
       case 0: batch_tile<1, 1>(sc.args, item.start, sc.tile_iters); break;
-      case 1: batch_tile<1, 4>(sc.args, item.start, sc.tile_iters); break;
-      default: batch_tile<4, 4>(sc.args, item.start, sc.tile_iters); break;
+      case 1: batch_tile<2, 2>(sc.args, item.start, sc.tile_iters); break;
+      default: batch_tile<8, 2>(sc.args, item.start, sc.tile_iters); break;
     }
   }
 }

@@ -70,7 +70,7 @@ static_assert(sizeof(BatchHeader) == 64, "batch header layout");
 
 struct BatchScene {
   NasgArgs args;
-  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (1, 4), 2 = (4, 4)
+  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (2, 2), 2 = (8, 2)
   int32_t tile_iters;
 };
 
@@ -80,7 +80,7 @@ struct BatchItem {
   int64_t start;       // first primitive of the tile
 };
 
-constexpr int kBatchLanes[3] = {1, 1, 4};
+constexpr int kBatchLanes[3] = {1, 2, 8};
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
                           uint32_t* counter, uint64_t token, int grid, hipStream_t s);

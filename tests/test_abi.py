@@ -117,7 +117,7 @@ def test_status_strings_and_tuning(lib):
     assert (out.lanes, out.views_per_lane, out.block) == (4, 2, 128)
     assert lib.nasg_set_tuning(1, 8, 16, 0, C.byref(L.NasgTuning(0, 0, 0))) == 0
     assert lib.nasg_get_tuning(1, 8, 16, 0, C.byref(out)) == 0
-    assert (out.lanes, out.views_per_lane) == (4, 4)
+    assert (out.lanes, out.views_per_lane) == (8, 2)           # built-in choice for V = 16
     assert lib.nasg_set_tuning(9, 8, 16, 0, C.byref(t)) == -5
 
 
@@ -145,7 +145,8 @@ def test_batched_rejects(lib):
     assert lib.nasg_batched_run(None, None) == -1
     empty = L.NasgBatch(FAKE, 0, 0, 0, 1, 0, 0)
     assert lib.nasg_batched_run(C.byref(empty), None) == 0      # nothing to launch
-    # the work list grows with the tile count: one tile per 4 x 256 primitives at V = 2
+    # the work list grows with the tile count: at V = 2 a primitive has 2 lanes, so
+    # one tile is 4 passes x 128 primitives
     sc[0].grad_rgb = FAKE
-    sc[0].p.n = 1024 * 3 + 1
+    sc[0].p.n = 512 * 3 + 1
     assert lib.nasg_batched_workspace_bytes(sc, 1, C.byref(t)) == need + 3 * 16
