@@ -13,6 +13,7 @@ namespace nasg {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
+constexpr double kInvPi = 0.318309886183790671537767526745028724;
 
 // ---------------------------------------------------------------- storage
 
@@ -85,7 +86,6 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 constexpr double kLn2Hi = 0.693145751953125;               // 2^-11 multiple
 constexpr double kLn2Lo = 1.4286068203094172321214581765680755e-06;
 constexpr double kLog2e = 1.442695040888963407359924681001892137;
-constexpr double kSqrtHalf = 0.707106781186547524400844362104849039;
 
 // 1/x for x > 0 normal: the hardware estimate (relative error < 5e-8
 // measured on gfx950) plus one Newton step (error ~ its square, ~2e-15).
@@ -104,29 +104,64 @@ __device__ inline double rsqrt64(double x) {
 }
 __device__ inline double sqrt64(double x) { return x * rsqrt64(x); }
 
-// ln(kappa) with kappa = 1 - h/2 in (0, 1]: kappa = m 2^e with m in
-// [1/sqrt 2, sqrt 2), ln m = 2 atanh(s), s = (m-1)/(m+1), summed as
-// 2 s (1 + s^2/3 + ... + s^12/13) with |s| <= 3 - 2 sqrt 2 (truncation
-// ~1e-12 relative). When e = 0, m - 1 = -h/2 is taken from h itself, so the
-// result keeps its relative accuracy however small h is.
-__device__ inline double log_kappa(double h, double kap) {
+// ---------------------------------------- envelope helpers (per lobe-view)
+// Where G is above the FP32 range floor, |X| <= ~1e2. A relative error eps of
+// ln kappa or of e^B then moves X by at most ~2e2 eps (the derivative of X
+// with respect to ln kappa is about X / ln kappa, and e^B - 1 enters as
+// 2 lam (e^B - 1) with lam (1 - e^B) <= ~50), so eps ~ 1e-10 keeps G
+// relatively accurate to ~1e-8. Near kappa = 1, where that derivative grows
+// to 2 lam (1 + tau) ~ 2e6, ln kappa keeps an absolute error ~1e-16.
+
+constexpr double kLn2 = 0.693147180559945309417232121458176568;
+
+// One bucket of the ln table: 1/c (rounded) and -ln of that rounded value.
+struct alignas(16) LogEntry {
+  double inv_c;
+  double ln_c;
+};
+constexpr int kLogBits = 7;
+constexpr int kLogEntries = 1 << kLogBits;
+
+// ln kappa for kappa in (0, 1), from a 128-entry table in LDS. kappa = m 2^e
+// with m in [1/2, 1); the top seven mantissa bits of m select c (the bucket
+// centre; c = 1 for the top bucket); r = m/c - 1 in one rounding, less
+// `dkap`, the known rounding error of kappa itself (kappa as computed minus
+// its exact value; it matters only in the top bucket, where r = kappa - 1);
+// |r| <= 1/256 and ln kappa = e ln2 + ln c + ln(1 + r) with ln(1 + r) summed
+// to r^4 (truncation |r|^5/5 <= 1.8e-13; relative r^4/5 in the top bucket,
+// so ln kappa stays relatively accurate however close kappa is to 1).
+__device__ inline double log_kappa(double kap, double dkap, const LogEntry* tab) {
   int e;
-  double m = frexp(kap, &e);
-  const bool low = m < kSqrtHalf;
-  m = low ? 2.0 * m : m;
-  e = low ? e - 1 : e;
-  const double num = (e == 0) ? -0.5 * h : m - 1.0;
-  const double s = num * rcp64(m + 1.0);
-  const double z = s * s;
-  double p = 1.0 / 13.0;
-  p = fma(p, z, 1.0 / 11.0);
-  p = fma(p, z, 1.0 / 9.0);
-  p = fma(p, z, 1.0 / 7.0);
-  p = fma(p, z, 1.0 / 5.0);
-  p = fma(p, z, 1.0 / 3.0);
-  p = fma(p, z, 1.0);
-  const double ef = static_cast<double>(e);
-  return fma(ef, kLn2Hi, fma(ef, kLn2Lo, 2.0 * s * p));
+  const double m = frexp(kap, &e);
+  const int j = (__double2hiint(m) >> (20 - kLogBits)) & (kLogEntries - 1);
+  const LogEntry t = tab[j];
+  const double r = fma(m, t.inv_c, -1.0) - dkap;
+  double p = fma(r, -0.25, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  const double lp = fma(p, r * r, r);
+  return fma(static_cast<double>(e), kLn2, t.ln_c + lp);
+}
+
+// e^B and e^B - 1 for B <= 0 on the envelope path: B = n ln2 + r in one FMA
+// (the rounding of ln2 costs |n| 2e-17, negligible wherever e^B matters),
+// e^r - 1 = r q(r) with q the Taylor series of (e^r - 1)/r to r^7/8!
+// (relative truncation r^8/9! <= 6e-10 at |r| = ln2/2, far smaller near
+// B = 0 where 2 lam (e^B - 1) is large). e^B - 1 is formed as e^B - 1, an
+// absolute error ~1e-16. B below -1e6 is clamped (e^B is 0 there).
+__device__ inline void env_exp(double B, double& eb, double& em1) {
+  B = fmax(B, -1.0e6);
+  const double n = rint(B * kLog2e);
+  const double r = fma(-n, kLn2, B);
+  double q = 1.0 / 40320.0;            // 1/8!
+  q = fma(q, r, 1.0 / 5040.0);
+  q = fma(q, r, 1.0 / 720.0);
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  eb = ldexp(fma(r, q, 1.0), static_cast<int>(n));
+  em1 = eb - 1.0;
 }
 
 // e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
@@ -155,20 +190,20 @@ __device__ inline void exp_em1(double B, double& eb, double& em1) {
   em1 = eb - 1.0;
 }
 
-// e^X as float for X <= 0: FP64 reduction X = n ln2 + r, then the hardware
-// base-2 exponential of the small remainder and an exact power-of-two scale.
-// X below -200 is clamped (e^-200 underflows FP32 to 0 either way).
+// e^X as float for X <= 0: FP64 reduction X = n ln2 + r in one FMA, then the
+// hardware base-2 exponential of the small remainder and an exact
+// power-of-two scale. X below -1e6 is clamped (e^X is 0 there).
 __device__ inline float exp_neg(double X) {
-  X = fmax(X, -200.0);
+  X = fmax(X, -1.0e6);
   const double n = rint(X * kLog2e);
-  double r = fma(-n, kLn2Hi, X);
-  r = fma(-n, kLn2Lo, r);
+  const double r = fma(-n, kLn2, X);
   const float p = __builtin_amdgcn_exp2f(static_cast<float>(r * kLog2e));
   return ldexpf(p, static_cast<int>(n));
 }
 
-// sin(pi x) and cos(pi x) in FP32 for x in [0, 1/4]: Taylor series of sine to
-// y^9 and cosine to y^10 in y = pi x <= pi/4 (truncation below 2e-8 relative).
+// sin(pi x) and cos(pi x) in FP32 for |x| <= 1/4: Taylor series of sine to
+// y^9 and cosine to y^10 in y = pi x, |y| <= pi/4 (truncation below 2e-8
+// relative).
 __device__ inline void sincospi_quarter(float x, float& s, float& c) {
   const float y = 3.14159265358979323846f * x;
   const float z = y * y;

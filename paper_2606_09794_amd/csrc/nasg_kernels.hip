@@ -1,18 +1,18 @@
 // NASGabor appearance evaluator: forward, backward and fused forward+backward
 // kernels for gfx950.
 //
-// Work mapping: each primitive owns P consecutive lanes of a wavefront; lane j
-// evaluates views v = v0 + j + P*t (t < VPL) of that primitive, so one
-// primitive's views never leave its lane group. Lobes are taken P at a time:
-// lane j loads lobe lc + j (structure-of-arrays, coalesced across primitives)
-// and prepares its per-lobe constants (FP64 frame, normaliser and its
-// log-derivatives) once; the group then walks those P lobes, reading each
-// lobe's constants from the lane that prepared it (ds_bpermute), and loops over
-// its own views with the per-view state (direction, upstream gradient, colour
-// and direction-gradient accumulators) in registers. Per-lobe gradient partial
-// sums are summed over the lane group with DPP row operations; the preparing
-// lane keeps its lobe's sums and, once the group has walked the P lobes, every
-// lane finalises and writes its own lobe - no atomics, fixed summation order.
+// Work mapping: each primitive owns P consecutive lanes of a wavefront. A
+// view chunk of P * VPL views is split into P view slots (slot j holds views
+// v0 + j + P*t, t < VPL: the direction, upstream gradient, colour and
+// direction-gradient accumulators, in registers). Lobes are taken P at a time
+// and lane j owns lobe lc + j: it loads that lobe (structure-of-arrays,
+// coalesced across primitives) and prepares its constants once (FP64 frame,
+// normaliser and its log-derivatives). Then, P times, every lane evaluates its
+// own lobe against the view slot it holds and passes the slot on to the next
+// lane of the group (ds_bpermute), so each owned lobe meets every view of the
+// chunk and each slot ends back in its home lane. A lobe's gradient sums never
+// leave its lane and a view's sums travel with its slot: no cross-lane
+// reduction per lobe, no atomics, a fixed summation order.
 //
 // Numerics: the view direction, the frame axes and the dot products d.x, d.z,
 // h = 1 - d.z and 1 - (d.z)^2 = h (2 - h) are FP64 (the lobes reach
@@ -43,43 +43,81 @@
 
 namespace nasg {
 
-// Value of lane `src` of this lane's group of P (ds_bpermute; P = 1 is a no-op).
-template <int P>
-__device__ inline float group_bcast(float x, int src) {
-  if constexpr (P == 1) {
-    return x;
-  } else {
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    const int addr = ((lane & ~(P - 1)) + src) << 2;
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+// ------------------------------------------------------------ ln table
+// ln x for x in [1, 2] at compile time: 2 atanh((x - 1)/(x + 1)) summed until
+// the terms vanish (|s| <= 1/3).
+constexpr double ce_log(double x) {
+  const double s = (x - 1.0) / (x + 1.0), z = s * s;
+  double term = s, sum = 0.0;
+  for (int i = 0; i < 40; ++i) {
+    sum += term / (2 * i + 1);
+    term *= z;
   }
+  return 2.0 * sum;
+}
+
+struct LogTable {
+  LogEntry e[kLogEntries];
+};
+
+// Bucket j covers m in [1/2 + j/256, 1/2 + (j + 1)/256); c is its centre, or
+// 1 for the top bucket. ln c is stored as -ln(1/c) of the rounded 1/c, so that
+// ln(m (1/c)) - ln(1/c) is ln m whatever the rounding of 1/c.
+constexpr LogTable make_log_table() {
+  LogTable t{};
+  for (int j = 0; j < kLogEntries; ++j) {
+    const double c = (j == kLogEntries - 1) ? 1.0 : 0.5 + (j + 0.5) / (2.0 * kLogEntries);
+    const double ic = 1.0 / c;
+    t.e[j].inv_c = ic;
+    t.e[j].ln_c = -ce_log(ic);
+  }
+  return t;
+}
+
+__constant__ const LogTable kLogTable = make_log_table();
+
+// Copies the ln table into this block's LDS (every thread of the block calls it).
+__device__ inline void load_log_table(LogEntry* lds) {
+  for (int t = threadIdx.x; t < kLogEntries; t += blockDim.x) lds[t] = kLogTable.e[t];
+  __syncthreads();
+}
+
+// Byte address, for ds_bpermute, of lane j + 1 (cyclically) of this lane's
+// group of P.
+template <int P>
+__device__ inline int group_next_addr() {
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  return ((lane & ~(P - 1)) | ((lane + 1) & (P - 1))) << 2;
+}
+
+// The value held by lane j + 1 of this lane's group (ds_bpermute; every lane
+// of the wavefront must be active).
+template <int P>
+__device__ inline float group_next(float x, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
 }
 
 template <int P>
-__device__ inline double group_bcast(double x, int src) {
-  if constexpr (P == 1) {
-    return x;
-  } else {
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    const int addr = ((lane & ~(P - 1)) + src) << 2;
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b & 0xffffffffll));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b >> 32));
-    return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                                (static_cast<long long>(lo) & 0xffffffffll));
-  }
+__device__ inline double group_next(double x, int addr) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              (static_cast<long long>(lo) & 0xffffffffll));
 }
 
 // One primitive-lane-group's work: primitive `prim` (may be >= n for tail
 // lanes, which compute on a real primitive and write nothing), lane j of P.
 template <int P, int VPL, bool BWD, bool BF16>
-__device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j) {
+__device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j,
+                                          const LogEntry* ltab) {
   using S = Store<BF16>;
   const int64_t N = a.n;
   const bool valid = prim < N;
   const int64_t i = valid ? prim : N - 1;  // tail lanes compute on a real primitive, write nothing
   const int V = a.v;
   const int K = a.k;
+  const int rot_addr = group_next_addr<P>();
 
   const float c00 = a.c0[3 * i + 0], c01 = a.c0[3 * i + 1], c02 = a.c0[3 * i + 2];
   double base0, base1, base2;
@@ -136,56 +174,53 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       }
     }
 
-    // ---- lobes, P at a time: lane j prepares lobe lc + j, the group shares it
+    // ---- lobes, P at a time: lane j owns lobe lc + j. The view slots travel
+    // round the lane group (lane j takes over the slot of lane j + 1 after
+    // every step), so after P steps every owned lobe has met every view of the
+    // chunk and every slot is back in its home lane. A lobe's gradient sums
+    // stay in the lane that owns it; a view's colour and direction gradient
+    // travel with its slot. A lane with no lobe left (K not a multiple of P)
+    // carries a zero normaliser and adds nothing.
     for (int lc = 0; lc < K; lc += P) {
-      const int lo = min(lc + j, K - 1);
+      const bool own = lc + j < K;
+      const int lo = own ? lc + j : K - 1;
       const int64_t oi = static_cast<int64_t>(lo) * N + i;
       const float4 q = S::load4(a.quat, oi);
       const float4 sh = S::load4(a.shape, oi);
-      const float ow0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
-      const float ow1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
-      const float ow2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
+      const float w0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
+      const float w1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
+      const float w2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
       // frame: x = M_x(q)/|q|^2, z = M_z(q)/|q|^2 (homogeneous rotation of q)
       const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
       const double ww = qw * qw, xx = qx * qx, yy = qy * qy, zz = qz * qz;
       const double is = rcp64(ww + xx + yy + zz);
-      const double oxa0 = (ww + xx - yy - zz) * is;
-      const double oxa1 = 2.0 * (qx * qy + qw * qz) * is;
-      const double oxa2 = 2.0 * (qx * qz - qw * qy) * is;
-      const double oza0 = 2.0 * (qx * qz + qw * qy) * is;
-      const double oza1 = 2.0 * (qy * qz - qw * qx) * is;
-      const double oza2 = (ww - xx - yy + zz) * is;
-      const double okrev = static_cast<double>(sh.z) * kInvTwoPi;
-      const double ozrev = static_cast<double>(sh.w) * kInvTwoPi;
+      const double xa0 = (ww + xx - yy - zz) * is;
+      const double xa1 = 2.0 * (qx * qy + qw * qz) * is;
+      const double xa2 = 2.0 * (qx * qz - qw * qy) * is;
+      const double za0 = 2.0 * (qx * qz + qw * qy) * is;
+      const double za1 = 2.0 * (qy * qz - qw * qx) * is;
+      const double za2 = (ww - xx - yy + zz) * is;
+      const double kh = static_cast<double>(sh.z) * kInvPi;
+      const double zh = static_cast<double>(sh.w) * kInvPi;
       const LobeNorm nm = lobe_norm(sh.x, sh.y, sh.z, sh.w, a.norm);
+      const float Nn = own ? nm.n : 0.f;
+      const float lam = sh.x, an = sh.y, kf = sh.z;
+      const float two_lam = 2.f * lam;
+      const double two_lamd = 2.0 * static_cast<double>(lam);
+      const double and_ = static_cast<double>(an);
+      const float two_an = 2.f * an;
+      const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
+                  xf2 = static_cast<float>(xa2);
+      const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
+                  zf2 = static_cast<float>(za2);
 
-      // reduced gradient sums of the lobe this lane prepared
-      float k_w0 = 0.f, k_w1 = 0.f, k_w2 = 0.f, k_G = 0.f, k_l = 0.f, k_a = 0.f, k_k = 0.f,
-            k_z = 0.f, k_x0 = 0.f, k_x1 = 0.f, k_x2 = 0.f, k_z0 = 0.f, k_z1 = 0.f, k_z2 = 0.f;
+      // gradient sums of the owned lobe
+      float acc_w0 = 0.f, acc_w1 = 0.f, acc_w2 = 0.f, acc_G = 0.f, acc_l = 0.f, acc_a = 0.f;
+      float acc_k = 0.f, acc_z = 0.f;
+      float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
 
-      const int nsub = min(P, K - lc);
-      for (int s = 0; s < nsub; ++s) {
-        const double xa0 = group_bcast<P>(oxa0, s), xa1 = group_bcast<P>(oxa1, s),
-                     xa2 = group_bcast<P>(oxa2, s);
-        const double za0 = group_bcast<P>(oza0, s), za1 = group_bcast<P>(oza1, s),
-                     za2 = group_bcast<P>(oza2, s);
-        const double krev = group_bcast<P>(okrev, s), zrev = group_bcast<P>(ozrev, s);
-        const float lam = group_bcast<P>(sh.x, s), an = group_bcast<P>(sh.y, s);
-        const float kf = group_bcast<P>(sh.z, s);
-        const float w0 = group_bcast<P>(ow0, s), w1 = group_bcast<P>(ow1, s),
-                    w2 = group_bcast<P>(ow2, s);
-        const float Nn = group_bcast<P>(nm.n, s);
-        const float two_lam = 2.f * lam;
-        const double two_lamd = 2.0 * static_cast<double>(lam);
-        const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
-                    xf2 = static_cast<float>(xa2);
-        const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
-                    zf2 = static_cast<float>(za2);
-
-        float acc_w0 = 0.f, acc_w1 = 0.f, acc_w2 = 0.f, acc_G = 0.f, acc_l = 0.f, acc_a = 0.f;
-        float acc_k = 0.f, acc_z = 0.f;
-        float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
-
+#pragma unroll 1
+      for (int step = 0; step < P; ++step) {
 #pragma unroll
         for (int t = 0; t < VPL; ++t) {
           // Branch-free. A view slot beyond V carries a real direction and a zero
@@ -200,29 +235,33 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
           const float dx = static_cast<float>(dxd);
           const float kap = fmaxf(static_cast<float>(kapd), 1e-30f);
-          // carrier phase in revolutions, reduced to the nearest integer
-          // (theta = 2 pi (f + integer), |f| <= 1/2). The carrier is cos^2(pi f)
-          // and dc/dtheta = -sign(f) sin(pi|f|) cos(pi|f|); both are evaluated
-          // from the smaller of |f| and 1/2 - |f| so they stay relatively
+          // carrier phase theta/pi = (k d.x + zeta)/pi, reduced to the nearest
+          // integer n: theta = pi (n + g), |g| <= 1/2. Even n is a carrier peak,
+          // c = cos^2(pi g/2); odd n a zero, c = sin^2(pi g/2); dc/dtheta is
+          // -sin(pi g/2) cos(pi g/2) at a peak and +sin cos at a zero. The
+          // offset g is exact in FP64, so c and dc/dtheta stay relatively
           // accurate at the carrier's peaks and zeros alike.
-          const double tr = fma(dxd, krev, zrev);
-          const double fr = tr - rint(tr);
-          const double fa = fabs(fr);
-          const bool near_peak = fa <= 0.25;
+          const double th = fma(dxd, kh, zh);
+          const double nh = rint(th);
           float sa, ca;
-          sincospi_quarter(static_cast<float>(0.25 - fabs(fa - 0.25)), sa, ca);  // min(|f|, 1/2-|f|)
-          const float sin_f = near_peak ? sa : ca;   // sin(pi |f|)
-          const float cos_f = near_peak ? ca : sa;   // cos(pi |f|)
-          const float car = cos_f * cos_f;
+          sincospi_quarter(0.5f * static_cast<float>(th - nh), sa, ca);
+          const bool peak = (static_cast<int>(nh) & 1) == 0;
+          const float cpk = peak ? ca : sa;
+          const float car = cpk * cpk;
+          const float scp = sa * ca;
           // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
           const bool pole = !(dend > 0.0);
           const double rden = pole ? 0.0 : rcp64(dend);
-          const double Ld = log_kappa(hd, fmax(kapd, 1e-300));
+          // kappa kept in [1e-300, 1 - 2^-53] (so kappa -> 1 stays in the top
+          // table bucket); near 1 the exact kappa is 1 - h/2, and
+          // (kappa - 1) + h/2 is its rounding error, exactly
+          const double kapc = fmin(fmax(kapd, 1e-300), 0x1.fffffffffffffp-1);
+          const double Ld = log_kappa(kapc, fma(0.5, hd, kapc - 1.0), ltab);
           const double ud = dxd * dxd * rden;        // tau / a
-          const double taud = static_cast<double>(an) * ud;
+          const double taud = and_ * ud;
           const double Ad = taud * Ld;               // ln E
           double Ekd, em1d;
-          exp_em1(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
+          env_exp(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
           const float pE = exp_neg(fma(two_lamd, em1d, Ad));
           const float Npe = live ? Nn * pE : 0.f;
           const float G = Npe * car;
@@ -246,12 +285,11 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             const float Ek = 1.f + em1;
             const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
             acc_a = fmaf(qG * T2 * L, u, acc_a);
-            const float fsg = fr < 0.0 ? 1.f : -1.f;          // -sign(f)
-            const float Sth = fsg * sin_f * cos_f * Npe;      // N p E dc/dtheta
+            const float Sth = (peak ? -scp : scp) * Npe;      // N p E dc/dtheta
             const float gS = gG * Sth;
             acc_k = fmaf(gS, dx, acc_k);
             acc_z += gS;
-            const float sx = fmaf(G * T2 * LR, 2.f * an * dx, Sth * kf);
+            const float sx = fmaf(G * T2 * LR, two_an * dx, Sth * kf);
             const float inv2k = 0.5f * __builtin_amdgcn_rcpf(kap);
             const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
                                   T2 * LR * tau * 2.f * static_cast<float>(dzd));
@@ -267,41 +305,31 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             gdir[t][2] = fmaf(gsx, xf2, fmaf(gsz, zf2, gdir[t][2]));
           }
         }
-
-        if constexpr (BWD) {
-          // group sums (computed by every lane: DPP needs all lanes active);
-          // the lane that prepared this lobe keeps them
-          const bool mine = (j == s);
-#define NASG_KEEP(dst, v)                  \
-  {                                        \
-    const float sum_ = group_sum<P>(v);    \
-    dst = mine ? sum_ : dst;               \
-  }
-          NASG_KEEP(k_w0, acc_w0);
-          NASG_KEEP(k_w1, acc_w1);
-          NASG_KEEP(k_w2, acc_w2);
-          NASG_KEEP(k_G, acc_G);
-          NASG_KEEP(k_l, acc_l);
-          NASG_KEEP(k_a, acc_a);
-          NASG_KEEP(k_k, acc_k);
-          NASG_KEEP(k_z, acc_z);
-          NASG_KEEP(k_x0, ax0);
-          NASG_KEEP(k_x1, ax1);
-          NASG_KEEP(k_x2, ax2);
-          NASG_KEEP(k_z0, az0);
-          NASG_KEEP(k_z1, az1);
-          NASG_KEEP(k_z2, az2);
-#undef NASG_KEEP
+        // pass the view slots on: this lane takes the slot of lane j + 1
+        if constexpr (P > 1) {
+#pragma unroll
+          for (int t = 0; t < VPL; ++t) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              dd[t][c] = group_next<P>(dd[t][c], rot_addr);
+              df[t][c] = group_next<P>(df[t][c], rot_addr);
+              col[t][c] = group_next<P>(col[t][c], rot_addr);
+              if constexpr (BWD) {
+                gr[t][c] = group_next<P>(gr[t][c], rot_addr);
+                gdir[t][c] = group_next<P>(gdir[t][c], rot_addr);
+              }
+            }
+          }
         }
       }
 
-      // every lane finalises the lobe it prepared (all lanes at once)
+      // the owning lane writes its lobe's gradients
       if constexpr (BWD) {
-        if (valid && lc + j < K) {
+        if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr) {
-            float4 gs = make_float4(fmaf(nm.dl, k_G, 2.f * k_l), fmaf(nm.da, k_G, k_a),
-                                    fmaf(nm.dk, k_G, k_k), fmaf(nm.dz, k_G, k_z));
+            float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
+                                    fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
             float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
             if (acc_mode) {
               const float4 o = *dst;
@@ -313,17 +341,13 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
             const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
             const float fis = static_cast<float>(is);
-            const float ox0 = static_cast<float>(oxa0), ox1 = static_cast<float>(oxa1),
-                        ox2 = static_cast<float>(oxa2);
-            const float oz0 = static_cast<float>(oza0), oz1 = static_cast<float>(oza1),
-                        oz2 = static_cast<float>(oza2);
-            const float rad = 2.f * (ox0 * k_x0 + ox1 * k_x1 + ox2 * k_x2 + oz0 * k_z0 +
-                                     oz1 * k_z1 + oz2 * k_z2);
+            const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 +
+                                     zf1 * az1 + zf2 * az2);
             float4 gq;
-            gq.x = 2.f * (fw * k_x0 + fz * k_x1 - fy * k_x2 + fy * k_z0 - fx * k_z1 + fw * k_z2);
-            gq.y = 2.f * (fx * k_x0 + fy * k_x1 + fz * k_x2 + fz * k_z0 - fw * k_z1 - fx * k_z2);
-            gq.z = 2.f * (-fy * k_x0 + fx * k_x1 - fw * k_x2 + fw * k_z0 + fz * k_z1 - fy * k_z2);
-            gq.w = 2.f * (-fz * k_x0 + fw * k_x1 + fx * k_x2 + fx * k_z0 + fy * k_z1 + fz * k_z2);
+            gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
+            gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
+            gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
+            gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
             gq.x = (gq.x - rad * fw) * fis;
             gq.y = (gq.y - rad * fx) * fis;
             gq.z = (gq.z - rad * fy) * fis;
@@ -337,7 +361,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           }
           if (a.g_rgbw != nullptr) {
             float* dst = a.g_rgbw + static_cast<int64_t>(lc + j) * 3 * N + i;
-            float r0 = k_w0, r1 = k_w1, r2 = k_w2;
+            float r0 = acc_w0, r1 = acc_w1, r2 = acc_w2;
             if (acc_mode) {
               r0 += dst[0];
               r1 += dst[N];
@@ -413,23 +437,44 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
 
 template <int P, int VPL, bool BWD, bool BF16>
 __global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
+  __shared__ LogEntry ltab[kLogEntries];
+  load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  nasg_body<P, VPL, BWD, BF16>(a, gt / P, static_cast<int>(gt & (P - 1)));
+  nasg_body<P, VPL, BWD, BF16>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
 }
 
 // ------------------------------------------------------- persistent batch
 
 template <int P, int VPL>
-__device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int iters) {
+__device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int iters,
+                                           const LogEntry* ltab) {
   constexpr int kPrimsPerPass = 256 / P;
   for (int m = 0; m < iters; ++m) {
     const int64_t base = start + static_cast<int64_t>(m) * kPrimsPerPass;
     if (base >= a.n) break;  // uniform across the block
-    nasg_body<P, VPL, true, false>(a, base + threadIdx.x / P, static_cast<int>(threadIdx.x & (P - 1)));
+    nasg_body<P, VPL, true, false>(a, base + threadIdx.x / P, static_cast<int>(threadIdx.x & (P - 1)),
+                                   ltab);
   }
 }
 
 __global__ void batch_reset(uint32_t* counter) { *counter = 0u; }
+
+// Loads a record that every lane of the wave reads at the same address and
+// pins each 32-bit word to a scalar register. Without it the compiler sees an
+// index that came through LDS as divergent and keeps the scene's pointers and
+// sizes in vector registers, with vector address arithmetic on every access.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "record size must be a multiple of 4 bytes");
+  constexpr int kWords = sizeof(T) / 4;
+  uint32_t w[kWords];
+  __builtin_memcpy(w, p, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
 
 // Pulls tiles from the queue until it is empty; every block exits when the
 // head passes n_items. A plan whose token does not match is not run.
@@ -441,20 +486,22 @@ void nasg_batched_kernel(const BatchHeader* hdr,
                                                            const BatchItem* items,
                                                            uint32_t* counter, uint64_t token) {
   __shared__ int s_item;
+  __shared__ LogEntry ltab[kLogEntries];
   if (hdr->token != token) return;
+  load_log_table(ltab);
   const int n_items = hdr->n_items;
   for (;;) {
     if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(counter, 1u));
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;
-    const BatchItem item = items[it];
-    const BatchScene& sc = scenes[item.scene];
+    const BatchItem item = load_uniform(items + it);
+    const BatchScene sc = load_uniform(scenes + item.scene);
     switch (sc.variant) {
-      case 0: batch_tile<1, 1>(sc.args, item.start, sc.tile_iters); break;
-      case 1: batch_tile<2, 2>(sc.args, item.start, sc.tile_iters); break;
-      default: batch_tile<8, 2>(sc.args, item.start, sc.tile_iters); break;
+      case 0: batch_tile<1, 1>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 1: batch_tile<2, 2>(sc.args, item.start, sc.tile_iters, ltab); break;
+      default: batch_tile<8, 2>(sc.args, item.start, sc.tile_iters, ltab); break;
     }
   }
 }
