@@ -130,16 +130,20 @@ constexpr int kLogEntries = 1 << kLogBits;
 // |r| <= 1/256 and ln kappa = e ln2 + ln c + ln(1 + r) with ln(1 + r) summed
 // to r^4 (truncation |r|^5/5 <= 1.8e-13; relative r^4/5 in the top bucket,
 // so ln kappa stays relatively accurate however close kappa is to 1).
-__device__ inline double log_kappa(double kap, double dkap, const LogEntry* tab) {
-  int e;
-  const double m = frexp(kap, &e);
-  const int j = (__double2hiint(m) >> (20 - kLogBits)) & (kLogEntries - 1);
-  const LogEntry t = tab[j];
+__device__ inline int log_bucket(double m) {
+  return (__double2hiint(m) >> (20 - kLogBits)) & (kLogEntries - 1);
+}
+__device__ inline double log_finish(double m, int e, const LogEntry& t, double dkap) {
   const double r = fma(m, t.inv_c, -1.0) - dkap;
   double p = fma(r, -0.25, 1.0 / 3.0);
   p = fma(p, r, -0.5);
   const double lp = fma(p, r * r, r);
   return fma(static_cast<double>(e), kLn2, t.ln_c + lp);
+}
+__device__ inline double log_kappa(double kap, double dkap, const LogEntry* tab) {
+  int e;
+  const double m = frexp(kap, &e);
+  return log_finish(m, e, tab[log_bucket(m)], dkap);
 }
 
 // e^B and e^B - 1 for B <= 0 on the envelope path: B = n ln2 + r in one FMA

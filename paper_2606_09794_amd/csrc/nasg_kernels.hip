@@ -232,6 +232,14 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double hd = 1.0 - dzd;
           const double kapd = 0.5 * (1.0 + dzd);
           const bool live = kapd > 0.0;
+          // kappa kept in [1e-300, 1 - 2^-53] (so kappa -> 1 stays in the top
+          // ln-table bucket); the table entry is fetched first, its use comes
+          // after the carrier and 1/(1 - (d.z)^2)
+          const double kapc = fmin(fmax(kapd, 1e-300), 0x1.fffffffffffffp-1);
+          int le;
+          const double lm = frexp(kapc, &le);
+          const LogEntry lt = ltab[log_bucket(lm)];
+          __builtin_amdgcn_sched_barrier(0);   // keep the table read ahead of the carrier work
           const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
           const float dx = static_cast<float>(dxd);
           const float kap = fmaxf(static_cast<float>(kapd), 1e-30f);
@@ -252,13 +260,12 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           // envelope exponent in FP64: X = 2 lam (E kappa - 1) + tau ln kappa
           const bool pole = !(dend > 0.0);
           const double rden = pole ? 0.0 : rcp64(dend);
-          // kappa kept in [1e-300, 1 - 2^-53] (so kappa -> 1 stays in the top
-          // table bucket); near 1 the exact kappa is 1 - h/2, and
-          // (kappa - 1) + h/2 is its rounding error, exactly
-          const double kapc = fmin(fmax(kapd, 1e-300), 0x1.fffffffffffffp-1);
-          const double Ld = log_kappa(kapc, fma(0.5, hd, kapc - 1.0), ltab);
           const double ud = dxd * dxd * rden;        // tau / a
           const double taud = and_ * ud;
+          __builtin_amdgcn_sched_barrier(0);
+          // near kappa = 1 the exact kappa is 1 - h/2, and (kappa - 1) + h/2 is
+          // its rounding error, exactly
+          const double Ld = log_finish(lm, le, lt, fma(0.5, hd, kapc - 1.0));
           const double Ad = taud * Ld;               // ln E
           double Ekd, em1d;
           env_exp(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
@@ -304,11 +311,9 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             gdir[t][1] = fmaf(gsx, xf1, fmaf(gsz, zf1, gdir[t][1]));
             gdir[t][2] = fmaf(gsx, xf2, fmaf(gsz, zf2, gdir[t][2]));
           }
-        }
-        // pass the view slots on: this lane takes the slot of lane j + 1
-        if constexpr (P > 1) {
-#pragma unroll
-          for (int t = 0; t < VPL; ++t) {
+          // pass this view slot on (this lane takes the slot of lane j + 1) as
+          // soon as it is done, so the transfer overlaps the next view's work
+          if constexpr (P > 1) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               dd[t][c] = group_next<P>(dd[t][c], rot_addr);
@@ -319,6 +324,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
                 gdir[t][c] = group_next<P>(gdir[t][c], rot_addr);
               }
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
