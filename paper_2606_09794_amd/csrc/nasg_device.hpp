@@ -194,15 +194,24 @@ __device__ inline void exp_em1(double B, double& eb, double& em1) {
   em1 = eb - 1.0;
 }
 
-// e^X as float for X <= 0: FP64 reduction X = n ln2 + r in one FMA, then the
-// hardware base-2 exponential of the small remainder and an exact
-// power-of-two scale. X below -1e6 is clamped (e^X is 0 there).
+// Nearest int of an integral double, saturated at the int range (the
+// conversion instruction's own behaviour, spelled out so that out-of-range
+// values are defined).
+__device__ __forceinline__ int sat_int(double n) {
+  int r;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(n));
+  return r;
+}
+
+// e^X as float for X <= 0: y = X log2(e) in FP64 (rounding |y| 1e-16), split
+// into its nearest integer n and |f| <= 1/2, then the hardware base-2
+// exponential of f and an exact power-of-two scale. Very negative X gives
+// 2^f with n saturated far below the FP32 range: 0.
 __device__ inline float exp_neg(double X) {
-  X = fmax(X, -1.0e6);
-  const double n = rint(X * kLog2e);
-  const double r = fma(-n, kLn2, X);
-  const float p = __builtin_amdgcn_exp2f(static_cast<float>(r * kLog2e));
-  return ldexpf(p, static_cast<int>(n));
+  const double y = X * kLog2e;
+  const double n = rint(y);
+  const float p = __builtin_amdgcn_exp2f(static_cast<float>(y - n));
+  return ldexpf(p, sat_int(n));
 }
 
 // sin(pi x) and cos(pi x) in FP32 for |x| <= 1/4: Taylor series of sine to

@@ -219,7 +219,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       float acc_k = 0.f, acc_z = 0.f;
       float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
 
-#pragma unroll 1
+#pragma unroll 2
       for (int step = 0; step < P; ++step) {
 #pragma unroll
         for (int t = 0; t < VPL; ++t) {
@@ -230,19 +230,19 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double dxd = dd[t][0] * xa0 + dd[t][1] * xa1 + dd[t][2] * xa2;
           const double dzd = dd[t][0] * za0 + dd[t][1] * za1 + dd[t][2] * za2;
           const double hd = 1.0 - dzd;
-          const double kapd = 0.5 * (1.0 + dzd);
-          const bool live = kapd > 0.0;
-          // kappa kept in [1e-300, 1 - 2^-53] (so kappa -> 1 stays in the top
-          // ln-table bucket); the table entry is fetched first, its use comes
-          // after the carrier and 1/(1 - (d.z)^2)
-          const double kapc = fmin(fmax(kapd, 1e-300), 0x1.fffffffffffffp-1);
+          const double opd = 1.0 + dzd;             // 2 kappa
+          const bool live = opd > 0.0;
+          // 2 kappa kept below 2 - 2^-52 (so kappa -> 1 stays in the top
+          // ln-table bucket); kappa = lm 2^(le - 1). The table entry is fetched
+          // first, its use comes after the carrier and 1/(1 - (d.z)^2).
+          const double opc = fmin(opd, 0x1.fffffffffffffp0);
           int le;
-          const double lm = frexp(kapc, &le);
+          const double lm = frexp(opc, &le);
           const LogEntry lt = ltab[log_bucket(lm)];
           __builtin_amdgcn_sched_barrier(0);   // keep the table read ahead of the carrier work
-          const double dend = hd * (2.0 - hd);      // 1 - (d.z)^2
+          const double dend = hd * opd;              // 1 - (d.z)^2
           const float dx = static_cast<float>(dxd);
-          const float kap = fmaxf(static_cast<float>(kapd), 1e-30f);
+          const float opf = fmaxf(static_cast<float>(opd), 1e-30f);
           // carrier phase theta/pi = (k d.x + zeta)/pi, reduced to the nearest
           // integer n: theta = pi (n + g), |g| <= 1/2. Even n is a carrier peak,
           // c = cos^2(pi g/2); odd n a zero, c = sin^2(pi g/2); dc/dtheta is
@@ -263,9 +263,9 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double ud = dxd * dxd * rden;        // tau / a
           const double taud = and_ * ud;
           __builtin_amdgcn_sched_barrier(0);
-          // near kappa = 1 the exact kappa is 1 - h/2, and (kappa - 1) + h/2 is
-          // its rounding error, exactly
-          const double Ld = log_finish(lm, le, lt, fma(0.5, hd, kapc - 1.0));
+          // near kappa = 1 (1 + d.z in [1, 2)) the exact kappa is 1 - h/2 and
+          // ((1 + d.z) - 2 + h)/2 is the rounding error of the computed one
+          const double Ld = log_finish(lm, le - 1, lt, 0.5 * ((opc - 2.0) + hd));
           const double Ad = taud * Ld;               // ln E
           double Ekd, em1d;
           env_exp(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
@@ -297,7 +297,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             acc_k = fmaf(gS, dx, acc_k);
             acc_z += gS;
             const float sx = fmaf(G * T2 * LR, two_an * dx, Sth * kf);
-            const float inv2k = 0.5f * __builtin_amdgcn_rcpf(kap);
+            const float inv2k = __builtin_amdgcn_rcpf(opf);   // 1/(2 kappa)
             const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
                                   T2 * LR * tau * 2.f * static_cast<float>(dzd));
             const float gsx = gG * sx, gsz = gG * sz;
@@ -442,7 +442,11 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
 }
 
 template <int P, int VPL, bool BWD, bool BF16>
-__global__ __launch_bounds__(256) void nasg_kernel(const NasgArgs a) {
+// One lane and one view per primitive run three waves per SIMD (the few spills
+// land in the once-per-lobe preparation); the other mappings keep two, where the
+// full register budget pays more than a third wave.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 && VPL == 1 ? 3 : 2)))
+void nasg_kernel(const NasgArgs a) {
   __shared__ LogEntry ltab[kLogEntries];
   load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
