@@ -296,10 +296,11 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             const float gS = gG * Sth;
             acc_k = fmaf(gS, dx, acc_k);
             acc_z += gS;
-            const float sx = fmaf(G * T2 * LR, two_an * dx, Sth * kf);
+            const float GTLR = G * T2 * LR;
+            const float sx = fmaf(GTLR, two_an * dx, Sth * kf);
             const float inv2k = __builtin_amdgcn_rcpf(opf);   // 1/(2 kappa)
-            const float sz = G * (fmaf(two_lam * (1.f + tau), Ek, tau) * inv2k +
-                                  T2 * LR * tau * 2.f * static_cast<float>(dzd));
+            const float sz = fmaf(GTLR * tau, 2.f * static_cast<float>(dzd),
+                                  G * inv2k * fmaf(fmaf(two_lam, tau, two_lam), Ek, tau));
             const float gsx = gG * sx, gsz = gG * sz;
             ax0 = fmaf(gsx, df[t][0], ax0);
             ax1 = fmaf(gsx, df[t][1], ax1);
