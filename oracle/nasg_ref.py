@@ -305,6 +305,24 @@ def forward_backward(quat, shape, rgbw, c0, grad_rgb, norm, means=None, cams=Non
     rgb, quat, shape, rgbw, c0 and means (or dirs)."""
     quat = np.asarray(quat, np.float64)
     ax, _, az = frame_from_quat(quat)
+    out, scale, axes = frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm,
+                                              means, cams, dirs)
+    gx_vec, gz_vec, sx_vec, sz_vec = axes
+    jx, jz = frame_jacobians(quat)
+    out["quat"] = (np.einsum("knci,knc->kni", jx, gx_vec)
+                   + np.einsum("knci,knc->kni", jz, gz_vec))
+    scale["quat"] = (np.einsum("knci,knc->kni", np.abs(jx), sx_vec)
+                     + np.einsum("knci,knc->kni", np.abs(jz), sz_vec))
+    return out, scale
+
+
+def frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm, means=None, cams=None,
+                           dirs=None):
+    """The evaluation for given lobe axes ax, az [K][N][3] (float64) and
+    lobe values shape = (lam, a, k, zeta), weights rgbw: colours and the
+    gradients w.r.t. shape, rgbw, c0 and the means (or dirs), each with its
+    rounding scale, plus the gradients w.r.t. the axes themselves,
+    (dL/dx, dL/dz, their scales), for the caller's frame parametrisation."""
     d, r = view_directions(means, cams, dirs)
     Cn, dC_dlam, dC_da, dC_dk, dC_dz = normaliser(shape, norm)
     t = lobe_terms(d, ax, az, shape, Cn)
@@ -384,12 +402,6 @@ def forward_backward(quat, shape, rgbw, c0, grad_rgb, norm, means=None, cams=Non
     sx_vec = np.einsum("kvn,vnc->knc", gGa * sxa, np.abs(d))
     sz_vec = np.einsum("kvn,vnc->knc", gGa * szva, np.abs(d))
 
-    jx, jz = frame_jacobians(quat)
-    out["quat"] = (np.einsum("knci,knc->kni", jx, gx_vec)
-                   + np.einsum("knci,knc->kni", jz, gz_vec))
-    scale["quat"] = (np.einsum("knci,knc->kni", np.abs(jx), sx_vec)
-                     + np.einsum("knci,knc->kni", np.abs(jz), sz_vec))
-
     out["shape"] = np.stack([g_l, g_a, g_k, g_z], -1)
     scale["shape"] = np.stack([s_l, s_a, s_k, s_z], -1)
 
@@ -410,7 +422,7 @@ def forward_backward(quat, shape, rgbw, c0, grad_rgb, norm, means=None, cams=Non
     key = "dirs" if dirs is not None else "means"
     out[key] = ge.sum(0)
     scale[key] = se.sum(0)
-    return out, scale
+    return out, scale, (gx_vec, gz_vec, sx_vec, sz_vec)
 
 
 def lobe_value(d, q, shape, norm):

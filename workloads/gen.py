@@ -22,6 +22,15 @@ Scene geometry: means uniform in [-5, 5]^3, camera centres uniform on the
 sphere of radius 10, which stands in for the paper's Mip-NeRF360-class scenes
 (roughly 3 M primitives per scene).
 
+With ``param="angles"`` the lobe slots hold the paper's own stored values
+instead, all before activation (Supplementary C): ``quat`` holds
+(u_theta, u_phi, u_psi, 0) with frame cosines tanh(u) drawn from N(0, 1);
+``shape`` holds (u_lambda, u_a, u_k, zeta) with u_lambda, u_a uniform in
+[0, ln 1e3] (so lambda = e^u and a = e^u are log-uniform in [1, 1e3] as
+above), u_k from N(0, 1) (k = 20 (tanh u + 1) spreads over the paper's
+[0, 40]) and zeta = 0 (the paper's carrier); ``rgbw`` holds the weights'
+u from N(0, 0.5^2) (w = tanh u).
+
 Nothing here evaluates the appearance model: the module draws, rounds to the
 storage dtype and gathers, so the oracle and the HIP path consume identical
 stored bits.
@@ -73,6 +82,7 @@ class Workload:
     shape_bits: Optional[np.ndarray] = None
     rgbw_bits: Optional[np.ndarray] = None
     orig: Optional[dict] = None  # float32 values before bf16 rounding
+    param: str = "quat"         # "quat" or "angles" (the paper's raw values)
 
     @property
     def evals(self) -> int:
@@ -97,6 +107,18 @@ def _draw_lobes(rng: np.random.Generator, k: int, n: int):
     return quat, np.ascontiguousarray(shape), rgbw, c0
 
 
+def _draw_paper_lobes(rng: np.random.Generator, k: int, n: int):
+    frame = np.zeros((k, n, 4), np.float32)
+    frame[..., :3] = rng.standard_normal((k, n, 3), dtype=np.float32)
+    ul = rng.uniform(0.0, math.log(1e3), (k, n)).astype(np.float32)
+    ua = rng.uniform(0.0, math.log(1e3), (k, n)).astype(np.float32)
+    uk = rng.standard_normal((k, n), dtype=np.float32)
+    shape = np.stack([ul, ua, uk, np.zeros_like(uk)], axis=-1)
+    rgbw = (0.5 * rng.standard_normal((k, 3, n), dtype=np.float32)).astype(np.float32)
+    c0 = (0.5 * rng.standard_normal((n, 3), dtype=np.float32)).astype(np.float32)
+    return frame, np.ascontiguousarray(shape), rgbw, c0
+
+
 def _draw_cams(rng: np.random.Generator, v: int) -> np.ndarray:
     g = rng.standard_normal((v, 3))
     return (10.0 * g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
@@ -104,11 +126,16 @@ def _draw_cams(rng: np.random.Generator, v: int) -> np.ndarray:
 
 def draw_workload(seed: int, n: int, k: int, v: int, *, dirs_mode: bool = False,
                   with_grad: bool = True, with_sh: bool = True, dtype: str = "f32",
-                  rng: Optional[np.random.Generator] = None) -> Workload:
+                  rng: Optional[np.random.Generator] = None, param: str = "quat") -> Workload:
     """Draw one workload. Order of draws: lobes, diffuse colour, geometry,
     upstream gradient, SH coefficients."""
     rng = np.random.default_rng(seed) if rng is None else rng
-    quat, shape, rgbw, c0 = _draw_lobes(rng, k, n)
+    if param == "quat":
+        quat, shape, rgbw, c0 = _draw_lobes(rng, k, n)
+    elif param == "angles":
+        quat, shape, rgbw, c0 = _draw_paper_lobes(rng, k, n)
+    else:
+        raise ValueError(f"unknown lobe parametrisation {param!r}")
     means = cams = dirs = None
     if dirs_mode:
         if v != 1:
@@ -120,7 +147,7 @@ def draw_workload(seed: int, n: int, k: int, v: int, *, dirs_mode: bool = False,
     grad_rgb = rng.standard_normal((v, n, 3), dtype=np.float32) if with_grad else None
     sh = (0.3 * rng.standard_normal((16, 3, n), dtype=np.float32)).astype(np.float32) if with_sh else None
     w = Workload(n=n, k=k, v=v, quat=quat, shape=shape, rgbw=rgbw, c0=c0, means=means,
-                 cams=cams, dirs=dirs, grad_rgb=grad_rgb, sh=sh)
+                 cams=cams, dirs=dirs, grad_rgb=grad_rgb, sh=sh, param=param)
     if dtype == "bf16":
         w.orig = {"quat": quat, "shape": shape, "rgbw": rgbw}
         w.quat_bits = f32_to_bf16_bits(quat)
@@ -187,7 +214,7 @@ def take_primitives(w: Workload, idx: np.ndarray) -> Workload:
         dirs=None if w.dirs is None else np.ascontiguousarray(w.dirs[idx]),
         grad_rgb=None if w.grad_rgb is None else np.ascontiguousarray(w.grad_rgb[:, idx]),
         sh=None if w.sh is None else np.ascontiguousarray(w.sh[:, :, idx]),
-        dtype=w.dtype,
+        dtype=w.dtype, param=w.param,
     )
     if w.dtype == "bf16":
         sub.quat_bits = np.ascontiguousarray(w.quat_bits[:, idx])
