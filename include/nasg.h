@@ -55,6 +55,26 @@
  * aligned for quat / shape); arithmetic and accumulation stay float32 (frame
  * and view geometry float64) and every gradient is written as float32 in the
  * float32 layout above.
+ *
+ * Lobe parametrisation (nasg_params.param)
+ * -----------------------------------------
+ * NASG_PARAM_QUAT   : the slots hold the values above.
+ * NASG_PARAM_ANGLES : the slots hold the paper's own stored values, before
+ *   activation (Supplementary C and its activation table):
+ *   quat  -> (u_theta, u_phi, u_psi, unused): frame cosines c = tanh(u),
+ *            sines s = +sqrt(1 - c^2),
+ *            z = (c_theta s_phi, s_theta s_phi, c_phi),
+ *            x = (c_theta c_phi c_psi - s_theta s_psi,
+ *                 s_theta c_phi c_psi + c_theta s_psi, -s_phi c_psi)
+ *            (the supplement calls the in-plane angle tau in the construction
+ *            and psi in the derivatives);
+ *   shape -> (u_lambda, u_a, u_k, zeta): lambda = e^u, a = e^u,
+ *            k = 20 (tanh u + 1), zeta unchanged (0 for the paper's carrier);
+ *   rgbw  -> u_w: w = tanh u.
+ *   Gradients are returned with respect to these raw values, in the same
+ *   slots (the unused fourth frame slot gets 0): Supplementary F's frame
+ *   derivatives chained through the activations, evaluated in a form that
+ *   stays finite where a cosine saturates.
  */
 #ifndef NASG_H
 #define NASG_H
@@ -73,7 +93,8 @@ typedef enum nasg_status {
                               [1, NASG_MAX_VIEWS], or dirs given with v != 1  */
   NASG_ERR_ALIGN = -3,     /* a pointer is not aligned as the layout requires */
   NASG_ERR_DTYPE = -4,     /* unknown storage dtype                           */
-  NASG_ERR_MODE = -5,      /* unknown normaliser or gradient mode             */
+  NASG_ERR_MODE = -5,      /* unknown normaliser, gradient mode or lobe
+                              parametrisation                                 */
   NASG_ERR_LAUNCH = -6,    /* the HIP runtime rejected a launch               */
   NASG_ERR_WORKSPACE = -7  /* batched: workspace missing, too small or stale  */
 } nasg_status;
@@ -94,6 +115,9 @@ typedef enum nasg_norm { NASG_NORM_EXACT = 0, NASG_NORM_APPROX = 1 } nasg_norm;
 
 typedef enum nasg_grad_mode { NASG_GRAD_OVERWRITE = 0, NASG_GRAD_ACCUMULATE = 1 } nasg_grad_mode;
 
+/* What the quat / shape / rgbw slots hold (see "Lobe parametrisation"). */
+typedef enum nasg_param { NASG_PARAM_QUAT = 0, NASG_PARAM_ANGLES = 1 } nasg_param;
+
 typedef struct nasg_params {
   const void* quat;   /* [K][N][4]  f32 or bf16                               */
   const void* shape;  /* [K][N][4]  f32 or bf16                               */
@@ -102,6 +126,8 @@ typedef struct nasg_params {
   int64_t n;          /* primitives                                           */
   int32_t k;          /* lobes per primitive, 1..NASG_MAX_LOBES               */
   int32_t dtype;      /* nasg_dtype of quat / shape / rgbw                    */
+  int32_t param;      /* nasg_param (NASG_ERR_MODE if unknown)                */
+  int32_t reserved;   /* set to 0                                             */
 } nasg_params;
 
 typedef struct nasg_views {

@@ -5,8 +5,10 @@ Supplementary C gives each lobe nine stored values, all pre-activation
 ("raw") numbers u that an optimiser updates directly:
 
 * frame: three cosines c = tanh(u) (activation table), with the sines
-  s = +sqrt(1 - c^2) (so theta, phi, psi lie in [0, pi]); the mean direction
-  and the tangent axis are
+  s = +sqrt(1 - c^2) (so theta, phi, psi lie in [0, pi]). For c = tanh(u)
+  that sine is sech(u) and is evaluated as 1/cosh(u): the same value, but
+  1 - c^2 of a rounded c near +-1 would lose the digits the sine needs. The
+  mean direction and the tangent axis are
       z = (c_theta s_phi, s_theta s_phi, c_phi),
       x = (c_theta c_phi c_psi - s_theta s_psi,
            s_theta c_phi c_psi + c_theta s_psi,
@@ -26,9 +28,9 @@ gradients with respect to the activated lam, a, k, zeta and w. The frame
 derivatives follow Supplementary F: dG/dc = dG/dx . dx/dc + dG/dz . dz/dc
 with the printed Jacobians of x and z in c_theta, c_phi, c_psi (they use
 ds/dc = -c/s); each activated gradient is then multiplied by the derivative
-of its activation (1 - c^2 for tanh, the value itself for exp,
-20 (1 - tanh^2) for k). The rounding scale of each raw gradient is the
-activated one times the absolute chain factor.
+of its activation (sech^2 u = 1 - tanh^2 u for tanh, evaluated as
+1/cosh^2(u); the value itself for exp; 20 sech^2 u for k). The rounding scale
+of each raw gradient is the activated one times the absolute chain factor.
 """
 from __future__ import annotations
 
@@ -51,21 +53,35 @@ def activate(frame_raw, shape_raw, rgbw_raw):
     return cos, shape, w
 
 
-def frame_from_cosines(cos):
-    """Columns x, y, z of R for cosines (c_theta, c_phi, c_psi) [..., 3]."""
+def sech(u):
+    """sech u = sqrt(1 - tanh^2 u) (the square root of d tanh(u)/du), as
+    1/cosh(u)."""
+    with np.errstate(over="ignore"):
+        return 1.0 / np.cosh(np.asarray(u, np.float64))
+
+
+def _sines(cos, sin):
+    return np.sqrt(1 - cos * cos) if sin is None else sin
+
+
+def frame_from_cosines(cos, sin=None):
+    """Columns x, y, z of R for cosines (c_theta, c_phi, c_psi) [..., 3]
+    (sines sqrt(1 - c^2), or ``sin`` when given)."""
     ct, cp, cs = cos[..., 0], cos[..., 1], cos[..., 2]
-    st, sp, ss = np.sqrt(1 - ct * ct), np.sqrt(1 - cp * cp), np.sqrt(1 - cs * cs)
+    sn = _sines(cos, sin)
+    st, sp, ss = sn[..., 0], sn[..., 1], sn[..., 2]
     z = np.stack([ct * sp, st * sp, cp], -1)
     x = np.stack([ct * cp * cs - st * ss, st * cp * cs + ct * ss, -sp * cs], -1)
     y = np.cross(z, x)
     return x, y, z
 
 
-def frame_cosine_jacobians(cos):
+def frame_cosine_jacobians(cos, sin=None):
     """dx/dc and dz/dc for c = (c_theta, c_phi, c_psi), each [..., 3 (axis
     component), 3 (which cosine)], as printed in Supplementary F."""
     ct, cp, cs = cos[..., 0], cos[..., 1], cos[..., 2]
-    st, sp, ss = np.sqrt(1 - ct * ct), np.sqrt(1 - cp * cp), np.sqrt(1 - cs * cs)
+    sn = _sines(cos, sin)
+    st, sp, ss = sn[..., 0], sn[..., 1], sn[..., 2]
     zero = np.zeros_like(ct)
     one = np.ones_like(ct)
     with np.errstate(all="ignore"):
@@ -83,7 +99,7 @@ def frame_cosine_jacobians(cos):
 def forward(frame_raw, shape_raw, rgbw_raw, c0, norm, means=None, cams=None, dirs=None):
     """rgb [V][N][3] and its rounding scale."""
     cos, shape, w = activate(frame_raw, shape_raw, rgbw_raw)
-    x, _, z = frame_from_cosines(cos)
+    x, _, z = frame_from_cosines(cos, sech(np.asarray(frame_raw, np.float64)[..., :3]))
     d, _ = R.view_directions(means, cams, dirs)
     Cn = R.normaliser(shape, norm)[0]
     t = R.lobe_terms(d, x, z, shape, Cn)
@@ -100,27 +116,27 @@ def forward_backward(frame_raw, shape_raw, rgbw_raw, c0, grad_rgb, norm, means=N
     rounding scale. Keys as ``nasg_ref.forward_backward``; "quat" holds the
     raw frame gradient (fourth component 0)."""
     cos, shape, w = activate(frame_raw, shape_raw, rgbw_raw)
-    x, _, z = frame_from_cosines(cos)
+    sin = sech(np.asarray(frame_raw, np.float64)[..., :3])
+    x, _, z = frame_from_cosines(cos, sin)
     out, scale, axes = R.frame_forward_backward(x, z, shape, w, c0, grad_rgb, norm,
                                                 means, cams, dirs)
     gx, gz, sx, sz = axes
-    jx, jz = frame_cosine_jacobians(cos)
+    jx, jz = frame_cosine_jacobians(cos, sin)
     g_cos = np.einsum("knci,knc->kni", jx, gx) + np.einsum("knci,knc->kni", jz, gz)
     s_cos = (np.einsum("knci,knc->kni", np.abs(jx), sx)
              + np.einsum("knci,knc->kni", np.abs(jz), sz))
-    dcos = 1 - cos * cos                                   # d tanh(u)/du
+    dcos = sin * sin                                       # d tanh(u)/du = sech^2 u
     zero = np.zeros(g_cos.shape[:-1] + (1,))
     out["quat"] = np.concatenate([g_cos * dcos, zero], -1)
     scale["quat"] = np.concatenate([s_cos * dcos, zero], -1)
 
     sr = np.asarray(shape_raw, np.float64)
-    tk = np.tanh(sr[..., 2])
-    chain = np.stack([shape[..., 0], shape[..., 1], 20.0 * (1 - tk * tk),
-                      np.ones_like(tk)], -1)
+    sk = sech(sr[..., 2])
+    chain = np.stack([shape[..., 0], shape[..., 1], 20.0 * sk * sk, np.ones_like(sk)], -1)
     out["shape"] = out["shape"] * chain
     scale["shape"] = scale["shape"] * np.abs(chain)
 
-    dw = 1 - w * w
+    dw = sech(rgbw_raw) ** 2
     out["rgbw"] = out["rgbw"] * dw
     scale["rgbw"] = scale["rgbw"] * dw
     return out, scale

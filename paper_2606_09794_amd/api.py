@@ -7,6 +7,12 @@ tensors in the layouts of ``include/nasg.h``:
     quat [K][N][4], shape [K][N][4], rgbw [K][3][N]   float32 or bfloat16
     c0 [N][3], means [N][3], cams [V][3] or dirs [N][3], grad_rgb [V][N][3]
     sh [16][3][N]                                       float32
+
+``param="quat"`` (default) reads quat / shape / rgbw as a quaternion frame,
+(lambda, a, k, zeta) and weights; ``param="angles"`` reads the paper's raw
+pre-activation values in the same slots (frame cosines tanh(u), lambda and a
+e^u, k = 20 (tanh u + 1), weights tanh u) and returns gradients with respect
+to those raw values.
 """
 from __future__ import annotations
 
@@ -18,6 +24,15 @@ import torch
 from . import _lib as L
 
 _NORMS = {"exact": L.NORM_EXACT, "approx": L.NORM_APPROX}
+_PARAMS = {"quat": L.PARAM_QUAT, "angles": L.PARAM_ANGLES}
+
+
+def _param_code(param) -> int:
+    if isinstance(param, str):
+        if param not in _PARAMS:
+            raise ValueError(f"param must be one of {sorted(_PARAMS)}")
+        return _PARAMS[param]
+    return int(param)
 
 
 def _norm_code(norm) -> int:
@@ -64,7 +79,7 @@ def _views(n: int, means, cams, dirs):
     return L.NasgViews(means.data_ptr(), cams.data_ptr(), None, v), v
 
 
-def _params(quat, shape, rgbw, c0):
+def _params(quat, shape, rgbw, c0, param="quat"):
     dt = quat.dtype
     if dt not in (torch.float32, torch.bfloat16):
         raise ValueError("lobe parameters must be float32 or bfloat16")
@@ -78,13 +93,13 @@ def _params(quat, shape, rgbw, c0):
         raise ValueError("expected quat/shape [K][N][4], rgbw [K][3][N], c0 [N][3]")
     code = L.NASG_F32 if dt == torch.float32 else L.NASG_BF16
     return L.NasgParams(quat.data_ptr(), shape.data_ptr(), rgbw.data_ptr(), c0.data_ptr(),
-                        n, k, code), k, n
+                        n, k, code, _param_code(param), 0), k, n
 
 
 def nasg_eval_fwd(quat, shape, rgbw, c0, *, means=None, cams=None, dirs=None, norm="exact",
-                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                  out: Optional[torch.Tensor] = None, param="quat") -> torch.Tensor:
     """Per-view colours rgb[V][N][3] (Section 4.2 model with NASGabor lobes)."""
-    p, k, n = _params(quat, shape, rgbw, c0)
+    p, k, n = _params(quat, shape, rgbw, c0, param)
     vw, v = _views(n, means, cams, dirs)
     if out is None:
         out = torch.empty((v, n, 3), device=quat.device, dtype=torch.float32)
@@ -103,12 +118,12 @@ def nasg_grad_buffers(k: int, n: int, device) -> Dict[str, torch.Tensor]:
 
 def nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb, *, means=None, cams=None, dirs=None,
                   norm="exact", grads: Optional[Dict[str, torch.Tensor]] = None,
-                  accumulate: bool = False, rgb_out: Optional[torch.Tensor] = None
-                  ) -> Dict[str, torch.Tensor]:
+                  accumulate: bool = False, rgb_out: Optional[torch.Tensor] = None,
+                  param="quat") -> Dict[str, torch.Tensor]:
     """Gradients of sum(grad_rgb * rgb) w.r.t. quat, shape, rgbw, c0 and the
     means (or dirs) as float32 tensors (dict keys quat, shape, rgbw, c0, geom).
     With ``rgb_out`` the forward colours are written in the same pass."""
-    p, k, n = _params(quat, shape, rgbw, c0)
+    p, k, n = _params(quat, shape, rgbw, c0, param)
     vw, v = _views(n, means, cams, dirs)
     _dev(grad_rgb, "grad_rgb")
     if tuple(grad_rgb.shape) != (v, n, 3):
@@ -175,7 +190,7 @@ class NasgBatchPlan:
         arr = (L.NasgScene * len(scenes))()
         self._keep = []
         for idx, sc in enumerate(scenes):
-            p, k, n = _params(sc["quat"], sc["shape"], sc["rgbw"], sc["c0"])
+            p, k, n = _params(sc["quat"], sc["shape"], sc["rgbw"], sc["c0"], sc.get("param", "quat"))
             vw, v = _views(n, sc.get("means"), sc.get("cams"), sc.get("dirs"))
             _dev(sc["grad_rgb"], "grad_rgb")
             if tuple(sc["grad_rgb"].shape) != (v, n, 3):
@@ -221,28 +236,32 @@ def get_tuning(kernel: int, k: int, v: int, dtype: int):
 # ------------------------------------------------------------------ autograd
 
 class NasgEval(torch.autograd.Function):
-    """rgb = NasgEval.apply(quat, shape, rgbw, c0, means, cams, dirs, norm).
+    """rgb = NasgEval.apply(quat, shape, rgbw, c0, means, cams, dirs, norm, param).
 
     Backward calls the analytic backward kernel; cams get no gradient. With
     bfloat16 lobe parameters the float32 gradients are rounded to bfloat16 to
-    match the parameter dtype."""
+    match the parameter dtype. With param="angles" the lobe tensors are the
+    paper's raw values and so are their gradients."""
 
     @staticmethod
-    def forward(ctx, quat, shape, rgbw, c0, means, cams, dirs, norm="exact"):
-        rgb = nasg_eval_fwd(quat, shape, rgbw, c0, means=means, cams=cams, dirs=dirs, norm=norm)
+    def forward(ctx, quat, shape, rgbw, c0, means, cams, dirs, norm="exact", param="quat"):
+        rgb = nasg_eval_fwd(quat, shape, rgbw, c0, means=means, cams=cams, dirs=dirs, norm=norm,
+                            param=param)
         ctx.save_for_backward(quat, shape, rgbw, c0, means, cams, dirs)
         ctx.norm = norm
+        ctx.param = param
         return rgb
 
     @staticmethod
     def backward(ctx, grad_rgb):
         quat, shape, rgbw, c0, means, cams, dirs = ctx.saved_tensors
         g = nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb.contiguous(), means=means, cams=cams,
-                          dirs=dirs, norm=ctx.norm)
+                          dirs=dirs, norm=ctx.norm, param=ctx.param)
         dt = quat.dtype
         gm = g["geom"] if dirs is None else None
         gd = g["geom"] if dirs is not None else None
-        return (g["quat"].to(dt), g["shape"].to(dt), g["rgbw"].to(dt), g["c0"], gm, None, gd, None)
+        return (g["quat"].to(dt), g["shape"].to(dt), g["rgbw"].to(dt), g["c0"], gm, None, gd,
+                None, None)
 
 
 class SH3Eval(torch.autograd.Function):

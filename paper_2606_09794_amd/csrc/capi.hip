@@ -79,6 +79,7 @@ int check_params(const nasg_params* p) {
   if (p == nullptr) return NASG_ERR_NULL;
   if (p->n < 0 || p->k < 1 || p->k > NASG_MAX_LOBES) return NASG_ERR_SHAPE;
   if (p->dtype != NASG_F32 && p->dtype != NASG_BF16) return NASG_ERR_DTYPE;
+  if (p->param != NASG_PARAM_QUAT && p->param != NASG_PARAM_ANGLES) return NASG_ERR_MODE;
   if (p->n == 0) return NASG_OK;  // nothing is read: pointers may be NULL
   if (p->quat == nullptr || p->shape == nullptr || p->rgbw == nullptr || p->c0 == nullptr)
     return NASG_ERR_NULL;
@@ -102,6 +103,7 @@ NasgArgs make_args(const nasg_params* p, const nasg_views* vw) {
   a.n = p->n;
   a.k = p->k;
   a.v = vw->v;
+  a.param = p->param;
   return a;
 }
 
@@ -115,7 +117,10 @@ int check_grad_ptrs(const float* grad_rgb, const nasg_grads* g, const float* rgb
 }
 
 // ---- persistent batches
-int batch_variant(int32_t v) { return v <= 1 ? 0 : (v <= 4 ? 1 : 2); }
+// lane mapping by view count, plus 3 for the paper's raw values
+int batch_variant(int32_t v, int32_t param) {
+  return (v <= 1 ? 0 : (v <= 4 ? 1 : 2)) + (param == NASG_PARAM_ANGLES ? 3 : 0);
+}
 
 struct BatchLayout {
   size_t items_off;
@@ -129,7 +134,7 @@ BatchLayout batch_layout(const nasg_scene* sc, int32_t n, int32_t tile_iters) {
   BatchLayout L{};
   L.items_off = align_up(sizeof(nasg::BatchHeader) + sizeof(nasg::BatchScene) * n, 64);
   for (int32_t s = 0; s < n; ++s) {
-    const int64_t tile = static_cast<int64_t>(tile_iters) * (256 / nasg::kBatchLanes[batch_variant(sc[s].views.v)]);
+    const int64_t tile = static_cast<int64_t>(tile_iters) * (256 / nasg::kBatchLanes[batch_variant(sc[s].views.v, sc[s].p.param)]);
     L.n_items += (sc[s].p.n + tile - 1) / tile;
   }
   L.total = L.items_off + sizeof(nasg::BatchItem) * static_cast<size_t>(L.n_items);
@@ -340,7 +345,7 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
     a.norm = norm;
     a.accumulate = 0;
     bs[s].args = a;
-    bs[s].variant = batch_variant(sc.views.v);
+    bs[s].variant = batch_variant(sc.views.v, sc.p.param);
     bs[s].tile_iters = tt.tile_iters;
     const int64_t tile = static_cast<int64_t>(tt.tile_iters) * (256 / nasg::kBatchLanes[bs[s].variant]);
     for (int64_t st0 = 0; st0 < sc.p.n; st0 += tile) {

@@ -262,6 +262,53 @@ __device__ inline void sincos_turns(double t, double& s, double& c) {
   c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
 }
 
+// ------------------------------------------- activations (paper's stored values)
+// e^B and e^B - 1 with the series of (e^r - 1)/r to r^12/13! (truncation
+// ~1e-17): for values that feed the lobe frame or the lobe parameters, whose
+// errors the envelope amplifies by up to lam (1 + a). B is clamped to
+// [-1400, 700] (beyond, e^B is 0 or overflows FP64 either way).
+__device__ inline void exp_full(double B, double& eb, double& em1) {
+  B = fmin(fmax(B, -1400.0), 700.0);
+  const double n = rint(B * kLog2e);
+  double r = fma(-n, kLn2Hi, B);
+  r = fma(-n, kLn2Lo, r);
+  double q = 1.0 / 6227020800.0;       // 1/13!
+  q = fma3(q, r, 1.0 / 479001600.0);
+  q = fma3(q, r, 1.0 / 39916800.0);
+  q = fma3(q, r, 1.0 / 3628800.0);
+  q = fma3(q, r, 1.0 / 362880.0);
+  q = fma3(q, r, 1.0 / 40320.0);
+  q = fma3(q, r, 1.0 / 5040.0);
+  q = fma3(q, r, 1.0 / 720.0);
+  q = fma3(q, r, 1.0 / 120.0);
+  q = fma3(q, r, 1.0 / 24.0);
+  q = fma3(q, r, 1.0 / 6.0);
+  q = fma3(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  eb = ldexp(fma(r, q, 1.0), static_cast<int>(n));
+  em1 = eb - 1.0;
+}
+
+// tanh u and sech u (= +sqrt(1 - tanh^2 u)) from one exponential q = e^{-|u|}:
+// tanh|u| = (1 - q)(1 + q)/(1 + q^2), sech u = 2 q/(1 + q^2); no overflow.
+__device__ inline void tanh_sech(double u, double& t, double& s) {
+  double q, qm1;
+  exp_full(-fabs(u), q, qm1);
+  const double inv = rcp64(fma(q, q, 1.0));
+  t = copysign(-qm1 * (1.0 + q) * inv, u);
+  s = 2.0 * q * inv;
+}
+
+// k = 20 (tanh u + 1) = 40/(1 + e^{-2u}) and dk/du = 20 sech^2 u
+// = 80 t/(1 + t)^2 with t = e^{-2|u|} (no overflow, no cancellation).
+__device__ inline void k_activation(double u, double& k, double& dk) {
+  double t, tm1;
+  exp_full(-2.0 * fabs(u), t, tm1);
+  const double inv = rcp64(1.0 + t);
+  k = 40.0 * (u >= 0.0 ? 1.0 : t) * inv;
+  dk = 80.0 * t * inv * inv;
+}
+
 // ------------------------------------------------------------- normaliser
 
 struct LobeNorm {
@@ -331,8 +378,7 @@ __device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
 // mode 0: 1 / closed-form integral (Section 5.1; the phase multiplies Psi by
 //         cos zeta);
 // mode 1: NASG normaliser lambda sqrt(1+a) / (2 pi (1 - e^{-2 lambda})).
-__device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, int mode) {
-  const double lam = lamf, a = af;
+__device__ inline LobeNorm lobe_norm(double lam, double a, double kd, double zd, int mode) {
   double e2l, em1_2l;
   exp_em1<true>(-2.0 * lam, e2l, em1_2l);
   const double dlam = -em1_2l;                    // 1 - e^{-2 lam}, relatively accurate
@@ -350,7 +396,7 @@ __device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, i
     out.dz = 0.f;
     return out;
   }
-  const double k = kf;
+  const double k = kd;
   const double L = lam * (1.0 + a);
   double F, dFs;
   exp_sinhc(L, k, F, dFs);
@@ -362,7 +408,7 @@ __device__ inline LobeNorm lobe_norm(float lamf, float af, float kf, float zf, i
   const double dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) * iD - 4.0 * L * F * e2L * iD * iD;
   const double dpsi_dk = -4.0 * L * k * dFs * iD;
   double sz, cz;
-  sincos_turns(static_cast<double>(zf) * kInvTwoPi, sz, cz);
+  sincos_turns(zd * kInvTwoPi, sz, cz);
   const double B = 1.0 + cz * psi;
   const double iB = rcp64(B);
   // I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) * B ;  N = 1/I

@@ -108,7 +108,7 @@ __device__ inline double group_next(double x, int addr) {
 
 // One primitive-lane-group's work: primitive `prim` (may be >= n for tail
 // lanes, which compute on a real primitive and write nothing), lane j of P.
-template <int P, int VPL, bool BWD, bool BF16>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG>
 __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j,
                                           const LogEntry* ltab) {
   using S = Store<BF16>;
@@ -187,28 +187,84 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       const int64_t oi = static_cast<int64_t>(lo) * N + i;
       const float4 q = S::load4(a.quat, oi);
       const float4 sh = S::load4(a.shape, oi);
-      const float w0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
-      const float w1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
-      const float w2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
-      // frame: x = M_x(q)/|q|^2, z = M_z(q)/|q|^2 (homogeneous rotation of q)
-      const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
-      const double ww = qw * qw, xx = qx * qx, yy = qy * qy, zz = qz * qz;
-      const double is = rcp64(ww + xx + yy + zz);
-      const double xa0 = (ww + xx - yy - zz) * is;
-      const double xa1 = 2.0 * (qx * qy + qw * qz) * is;
-      const double xa2 = 2.0 * (qx * qz - qw * qy) * is;
-      const double za0 = 2.0 * (qx * qz + qw * qy) * is;
-      const double za1 = 2.0 * (qy * qz - qw * qx) * is;
-      const double za2 = (ww - xx - yy + zz) * is;
-      const double kh = static_cast<double>(sh.z) * kInvPi;
-      const double zh = static_cast<double>(sh.w) * kInvPi;
-      const LobeNorm nm = lobe_norm(sh.x, sh.y, sh.z, sh.w, a.norm);
+      float w0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
+      float w1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
+      float w2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
+      double xa0, xa1, xa2, za0, za1, za2, lamd, ad, kd;
+      // what the gradient write-out needs besides the sums: the frame's own
+      // parameters (f*) and, for the paper's raw values, the derivative of
+      // each value's activation
+      float f0, f1, f2, f3, f4, f5;
+      float dlam_du = 1.f, da_du = 1.f, dk_du = 1.f, dw0 = 1.f, dw1 = 1.f, dw2 = 1.f;
+      if constexpr (ANG) {
+        // Supplementary C: cosines tanh(u) with sines sqrt(1 - c^2) = sech(u),
+        // z = (c_t s_p, s_t s_p, c_p),
+        // x = (c_t c_p c_s - s_t s_s, s_t c_p c_s + c_t s_s, -s_p c_s);
+        // lam = e^u, a = e^u, k = 20 (tanh u + 1), w = tanh u
+        double ct, st, cp, sp, cs, ss;
+        tanh_sech(q.x, ct, st);
+        tanh_sech(q.y, cp, sp);
+        tanh_sech(q.z, cs, ss);
+        za0 = ct * sp;
+        za1 = st * sp;
+        za2 = cp;
+        xa0 = ct * cp * cs - st * ss;
+        xa1 = st * cp * cs + ct * ss;
+        xa2 = -sp * cs;
+        double em1, dkd;
+        exp_full(sh.x, lamd, em1);
+        exp_full(sh.y, ad, em1);
+        k_activation(sh.z, kd, dkd);
+        double t, sc;
+        tanh_sech(w0, t, sc);
+        w0 = static_cast<float>(t);
+        dw0 = static_cast<float>(sc * sc);
+        tanh_sech(w1, t, sc);
+        w1 = static_cast<float>(t);
+        dw1 = static_cast<float>(sc * sc);
+        tanh_sech(w2, t, sc);
+        w2 = static_cast<float>(t);
+        dw2 = static_cast<float>(sc * sc);
+        f0 = static_cast<float>(ct);
+        f1 = static_cast<float>(st);
+        f2 = static_cast<float>(cp);
+        f3 = static_cast<float>(sp);
+        f4 = static_cast<float>(cs);
+        f5 = static_cast<float>(ss);
+        dlam_du = static_cast<float>(lamd);
+        da_du = static_cast<float>(ad);
+        dk_du = static_cast<float>(dkd);
+      } else {
+        // frame: x = M_x(q)/|q|^2, z = M_z(q)/|q|^2 (homogeneous rotation of q)
+        const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+        const double ww = qw * qw, xx = qx * qx, yy = qy * qy, zz = qz * qz;
+        const double is = rcp64(ww + xx + yy + zz);
+        xa0 = (ww + xx - yy - zz) * is;
+        xa1 = 2.0 * (qx * qy + qw * qz) * is;
+        xa2 = 2.0 * (qx * qz - qw * qy) * is;
+        za0 = 2.0 * (qx * qz + qw * qy) * is;
+        za1 = 2.0 * (qy * qz - qw * qx) * is;
+        za2 = (ww - xx - yy + zz) * is;
+        lamd = sh.x;
+        ad = sh.y;
+        kd = sh.z;
+        f0 = q.x;
+        f1 = q.y;
+        f2 = q.z;
+        f3 = q.w;
+        f4 = static_cast<float>(is);
+        f5 = 0.f;
+      }
+      const double zd = sh.w;
+      const double kh = kd * kInvPi;
+      const double zh = zd * kInvPi;
+      const LobeNorm nm = lobe_norm(lamd, ad, kd, zd, a.norm);
       const float Nn = own ? nm.n : 0.f;
-      const float lam = sh.x, an = sh.y, kf = sh.z;
-      const float two_lam = 2.f * lam;
-      const double two_lamd = 2.0 * static_cast<double>(lam);
-      const double and_ = static_cast<double>(an);
-      const float two_an = 2.f * an;
+      const float kf = static_cast<float>(kd);
+      const float two_lam = static_cast<float>(2.0 * lamd);
+      const double two_lamd = 2.0 * lamd;
+      const double and_ = ad;
+      const float two_an = static_cast<float>(2.0 * ad);
       const float xf0 = static_cast<float>(xa0), xf1 = static_cast<float>(xa1),
                   xf2 = static_cast<float>(xa2);
       const float zf0 = static_cast<float>(za0), zf1 = static_cast<float>(za1),
@@ -335,8 +391,9 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr) {
-            float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l), fmaf(nm.da, acc_G, acc_a),
-                                    fmaf(nm.dk, acc_G, acc_k), fmaf(nm.dz, acc_G, acc_z));
+            float4 gs = make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l) * dlam_du,
+                                    fmaf(nm.da, acc_G, acc_a) * da_du,
+                                    fmaf(nm.dk, acc_G, acc_k) * dk_du, fmaf(nm.dz, acc_G, acc_z));
             float4* dst = reinterpret_cast<float4*>(a.g_shape) + li;
             if (acc_mode) {
               const float4 o = *dst;
@@ -345,20 +402,39 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             *dst = gs;
           }
           if (a.g_quat != nullptr) {
-            // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
-            const float fw = q.x, fx = q.y, fy = q.z, fz = q.w;
-            const float fis = static_cast<float>(is);
-            const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 +
-                                     zf1 * az1 + zf2 * az2);
+            // (ax, az) = (dL/dx, dL/dz)
             float4 gq;
-            gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
-            gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
-            gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
-            gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
-            gq.x = (gq.x - rad * fw) * fis;
-            gq.y = (gq.y - rad * fx) * fis;
-            gq.z = (gq.z - rad * fy) * fis;
-            gq.w = (gq.w - rad * fz) * fis;
+            if constexpr (ANG) {
+              // through the raw values u (dc/du = s^2, ds/du = -c s), which keeps
+              // the printed 1/s of Supplementary F's Jacobians out:
+              //   dx/du_t = s_t (x_1, -x_0, 0),  dz/du_t = s_t (z_1, -z_0, 0),
+              //   dx/du_p = s_p c_s z,           dz/du_p = -s_p e_p,
+              //   dx/du_s = s_s (s_s e_p - c_s e_t),
+              // e_p = (c_t c_p, s_t c_p, -s_p), e_t = (-s_t, c_t, 0)
+              const float ct = f0, st = f1, cp = f2, sp = f3, cs = f4, ss = f5;
+              const float ep0 = ct * cp, ep1 = st * cp, ep2 = -sp;
+              const float xz = ax0 * zf0 + ax1 * zf1 + ax2 * zf2;
+              const float xep = ax0 * ep0 + ax1 * ep1 + ax2 * ep2;
+              const float zep = az0 * ep0 + az1 * ep1 + az2 * ep2;
+              const float xet = ax1 * ct - ax0 * st;
+              gq.x = st * (ax0 * xf1 - ax1 * xf0 + az0 * zf1 - az1 * zf0);
+              gq.y = sp * (cs * xz - zep);
+              gq.z = ss * (ss * xep - cs * xet);
+              gq.w = 0.f;
+            } else {
+              // dL/dq = (J_x^T gx + J_z^T gz)/|q|^2 - 2 q (x.gx + z.gz)/|q|^2
+              const float fw = f0, fx = f1, fy = f2, fz = f3, fis = f4;
+              const float rad = 2.f * (xf0 * ax0 + xf1 * ax1 + xf2 * ax2 + zf0 * az0 +
+                                       zf1 * az1 + zf2 * az2);
+              gq.x = 2.f * (fw * ax0 + fz * ax1 - fy * ax2 + fy * az0 - fx * az1 + fw * az2);
+              gq.y = 2.f * (fx * ax0 + fy * ax1 + fz * ax2 + fz * az0 - fw * az1 - fx * az2);
+              gq.z = 2.f * (-fy * ax0 + fx * ax1 - fw * ax2 + fw * az0 + fz * az1 - fy * az2);
+              gq.w = 2.f * (-fz * ax0 + fw * ax1 + fx * ax2 + fx * az0 + fy * az1 + fz * az2);
+              gq.x = (gq.x - rad * fw) * fis;
+              gq.y = (gq.y - rad * fx) * fis;
+              gq.z = (gq.z - rad * fy) * fis;
+              gq.w = (gq.w - rad * fz) * fis;
+            }
             float4* dst = reinterpret_cast<float4*>(a.g_quat) + li;
             if (acc_mode) {
               const float4 o = *dst;
@@ -368,7 +444,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           }
           if (a.g_rgbw != nullptr) {
             float* dst = a.g_rgbw + static_cast<int64_t>(lc + j) * 3 * N + i;
-            float r0 = acc_w0, r1 = acc_w1, r2 = acc_w2;
+            float r0 = acc_w0 * dw0, r1 = acc_w1 * dw1, r2 = acc_w2 * dw2;
             if (acc_mode) {
               r0 += dst[0];
               r1 += dst[N];
@@ -442,7 +518,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
   }
 }
 
-template <int P, int VPL, bool BWD, bool BF16>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG>
 // One lane and one view per primitive run three waves per SIMD (the few spills
 // land in the once-per-lobe preparation); the other mappings keep two, where the
 // full register budget pays more than a third wave.
@@ -451,20 +527,20 @@ void nasg_kernel(const NasgArgs a) {
   __shared__ LogEntry ltab[kLogEntries];
   load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  nasg_body<P, VPL, BWD, BF16>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
+  nasg_body<P, VPL, BWD, BF16, ANG>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
 }
 
 // ------------------------------------------------------- persistent batch
 
-template <int P, int VPL>
+template <int P, int VPL, bool ANG>
 __device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int iters,
                                            const LogEntry* ltab) {
   constexpr int kPrimsPerPass = 256 / P;
   for (int m = 0; m < iters; ++m) {
     const int64_t base = start + static_cast<int64_t>(m) * kPrimsPerPass;
     if (base >= a.n) break;  // uniform across the block
-    nasg_body<P, VPL, true, false>(a, base + threadIdx.x / P, static_cast<int>(threadIdx.x & (P - 1)),
-                                   ltab);
+    nasg_body<P, VPL, true, false, ANG>(a, base + threadIdx.x / P,
+                                        static_cast<int>(threadIdx.x & (P - 1)), ltab);
   }
 }
 
@@ -510,9 +586,12 @@ void nasg_batched_kernel(const BatchHeader* hdr,
     const BatchItem item = load_uniform(items + it);
     const BatchScene sc = load_uniform(scenes + item.scene);
     switch (sc.variant) {
-      case 0: batch_tile<1, 1>(sc.args, item.start, sc.tile_iters, ltab); break;
-      case 1: batch_tile<2, 2>(sc.args, item.start, sc.tile_iters, ltab); break;
-      default: batch_tile<8, 2>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 3: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 4: batch_tile<2, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+      default: batch_tile<8, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
     }
   }
 }
@@ -529,21 +608,27 @@ hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, cons
 
 // ------------------------------------------------------------ instantiation
 
-template <int P, int VPL, bool BWD, bool BF16>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG>
 static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
   const int64_t threads = a.n * P;
   const int64_t grid = (threads + block - 1) / block;
-  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16>), dim3(static_cast<unsigned>(grid)),
+  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG>), dim3(static_cast<unsigned>(grid)),
                      dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
+template <int P, int VPL, bool ANG>
+static hipError_t launch_pa(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s) {
+  if (bwd) return bf16 ? launch_one<P, VPL, true, true, ANG>(a, block, s)
+                       : launch_one<P, VPL, true, false, ANG>(a, block, s);
+  return bf16 ? launch_one<P, VPL, false, true, ANG>(a, block, s)
+              : launch_one<P, VPL, false, false, ANG>(a, block, s);
+}
+
 template <int P, int VPL>
 static hipError_t launch_pv(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s) {
-  if (bwd) return bf16 ? launch_one<P, VPL, true, true>(a, block, s)
-                       : launch_one<P, VPL, true, false>(a, block, s);
-  return bf16 ? launch_one<P, VPL, false, true>(a, block, s)
-              : launch_one<P, VPL, false, false>(a, block, s);
+  return a.param == kParamAngles ? launch_pa<P, VPL, true>(a, bwd, bf16, block, s)
+                                 : launch_pa<P, VPL, false>(a, bwd, bf16, block, s);
 }
 
 hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,

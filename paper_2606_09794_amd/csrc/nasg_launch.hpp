@@ -26,7 +26,12 @@ struct NasgArgs {
   int32_t v;
   int32_t norm;
   int32_t accumulate;
+  int32_t param;       // 0: quaternion + (lam, a, k, zeta); 1: the paper's raw values
+  int32_t pad;
 };
+
+constexpr int kParamQuat = 0;
+constexpr int kParamAngles = 1;
 
 struct ShArgs {
   const float* sh;
@@ -70,7 +75,8 @@ static_assert(sizeof(BatchHeader) == 64, "batch header layout");
 
 struct BatchScene {
   NasgArgs args;
-  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (2, 2), 2 = (8, 2)
+  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (2, 2), 2 = (8, 2);
+                       // 3..5: the same for the paper's raw values
   int32_t tile_iters;
 };
 
@@ -80,7 +86,7 @@ struct BatchItem {
   int64_t start;       // first primitive of the tile
 };
 
-constexpr int kBatchLanes[3] = {1, 2, 8};
+constexpr int kBatchLanes[6] = {1, 2, 8, 1, 2, 8};
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
                           uint32_t* counter, uint64_t token, int grid, hipStream_t s);

@@ -4,6 +4,7 @@ import numpy as np
 import torch
 
 from oracle import metrics as M
+from oracle import nasg_paper as Pp
 from oracle import nasg_ref as R
 from oracle import sh3_ref as S
 
@@ -31,7 +32,10 @@ def dgeo(d):
 
 
 def oracle_nasg(w, norm):
-    out, scale = R.forward_backward(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, NORMS[norm], **geo(w))
+    """The oracle for the workload's lobe parametrisation (quaternion or the
+    paper's raw values)."""
+    fb = Pp.forward_backward if getattr(w, "param", "quat") == "angles" else R.forward_backward
+    out, scale = fb(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, NORMS[norm], **geo(w))
     key = "dirs" if w.dirs is not None else "means"
     out["geom"], scale["geom"] = out.pop(key), scale.pop(key)
     return out, scale

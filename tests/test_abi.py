@@ -54,6 +54,7 @@ def fwd(lib, p, v, rgb=FAKE, norm=0):
     (dict(quat=None), -1), (dict(quat=FAKE + 4), -3), (dict(c0=FAKE + 2), -3),
     (dict(v=0), -2), (dict(v=5000), -2), (dict(dirs=FAKE, v=2), -2), (dict(cams=None), -1),
     (dict(rgb=None), -1), (dict(rgb=FAKE + 1), -3), (dict(norm=7), -5),
+    (dict(param=2), -5), (dict(param=-1), -5),
 ])
 def test_fwd_rejects(lib, case, code):
     case = dict(case)
