@@ -178,13 +178,15 @@ def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
     before bf16 rounding: the quantisation cost)."""
     import workloads as W
     from oracle import metrics as M
+    from oracle import nasg_paper as Pp
     from oracle import nasg_ref as R
     idx = np.sort(np.random.default_rng(seed).choice(w.n, size=min(n_sample, w.n), replace=False))
     sub = W.take_primitives(w, idx)
     src = sub.orig if orig else {"quat": sub.quat, "shape": sub.shape, "rgbw": sub.rgbw}
-    ref, scale = R.forward_backward(src["quat"], src["shape"], src["rgbw"], sub.c0, sub.grad_rgb,
-                                    R.NORM_EXACT if norm == "exact" else R.NORM_APPROX,
-                                    means=sub.means, cams=sub.cams)
+    fb = Pp.forward_backward if w.param == "angles" else R.forward_backward
+    ref, scale = fb(src["quat"], src["shape"], src["rgbw"], sub.c0, sub.grad_rgb,
+                    R.NORM_EXACT if norm == "exact" else R.NORM_APPROX,
+                    means=sub.means, cams=sub.cams)
     ref["geom"], scale["geom"] = ref.pop("means"), scale.pop("means")
     sel = {"rgb": lambda t: t[:, idx], "quat": lambda t: t[:, idx], "shape": lambda t: t[:, idx],
            "rgbw": lambda t: t[:, :, idx], "c0": lambda t: t[idx], "geom": lambda t: t[idx]}
@@ -260,6 +262,37 @@ def bench_other(args, log):
                                                          "algorithmic_bytes_per_launch": ab32}},
                    parity_sampled_max_scaled_error=par,
                    bf16_quantisation_cost_vs_fp32_values=qcost)
+    elif args.workload == "paper-params":
+        t0 = time.perf_counter()
+        w = W.draw_workload(7, args.n, 8, args.views, with_sh=False, param="angles")
+        log(f"generated N={w.n} K={w.k} V={w.v} (raw values) in {time.perf_counter() - t0:.1f}s")
+        d = upload(w)
+        n, k, v = w.n, w.k, w.v
+        g = P.nasg_grad_buffers(k, n, "cuda")
+        rgb = torch.empty((v, n, 3), device="cuda")
+        fn = lambda dd, par: P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"],  # noqa: E731
+                                             dd["grad_rgb"], means=dd["means"], cams=dd["cams"],
+                                             norm=args.norm, grads=g, rgb_out=rgb, param=par)
+        ms = time_launches(lambda: fn(d, "angles"), args.steps, args.warmup)
+        fn(d, "angles")
+        torch.cuda.synchronize()
+        par = _sampled(w, dict(g, rgb=rgb), args.norm)
+        del d
+        wq = W.draw_workload(7, n, k, v, with_sh=False)
+        dq = upload(wq)
+        msq = time_launches(lambda: fn(dq, "quat"), args.steps, args.warmup)
+        ab = algorithmic_bytes(n, k, v)
+        res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
+                   config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
+                                       f"the paper's raw lobe values (three frame cosines and "
+                                       f"activations), FP32, {args.norm} normaliser",
+                           "primitives": n, "lobes": k, "views": v, "param": "angles"},
+                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   compare={"quaternion_parametrisation_same_sizes": {
+                       "ms": round(msq, 4), "G_evals_s": round(n * v / msq / 1e6, 4)}},
+                   parity_sampled_max_scaled_error=par)
     elif args.workload == "uneven-batch":
         t0 = time.perf_counter()
         scenes = W.config4()
@@ -344,10 +377,11 @@ def main():
                          "device copy of --copy-mib MiB for calibrating byte counters")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "single-camera", "bf16-k16", "uneven-batch"],
+                    choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params"],
                     help="headline: K=8, 3 M primitives x 16 cameras; single-camera: K=8, 1 M x 1; "
                          "bf16-k16: K=16, 6 M x 8, bf16 storage; uneven-batch: 32 scenes in one "
-                         "persistent launch")
+                         "persistent launch; paper-params: the headline sizes with the paper's raw "
+                         "lobe values")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the path shards by primitive with no "
