@@ -93,8 +93,8 @@ typedef enum nasg_status {
                               [1, NASG_MAX_VIEWS], or dirs given with v != 1  */
   NASG_ERR_ALIGN = -3,     /* a pointer is not aligned as the layout requires */
   NASG_ERR_DTYPE = -4,     /* unknown storage dtype                           */
-  NASG_ERR_MODE = -5,      /* unknown normaliser, gradient mode or lobe
-                              parametrisation                                 */
+  NASG_ERR_MODE = -5,      /* unknown normaliser, gradient mode, lobe
+                              parametrisation or lobe family                  */
   NASG_ERR_LAUNCH = -6,    /* the HIP runtime rejected a launch               */
   NASG_ERR_WORKSPACE = -7  /* batched: workspace missing, too small or stale  */
 } nasg_status;
@@ -118,6 +118,36 @@ typedef enum nasg_grad_mode { NASG_GRAD_OVERWRITE = 0, NASG_GRAD_ACCUMULATE = 1 
 /* What the quat / shape / rgbw slots hold (see "Lobe parametrisation"). */
 typedef enum nasg_param { NASG_PARAM_QUAT = 0, NASG_PARAM_ANGLES = 1 } nasg_param;
 
+/* Lobe family (the spherical functions of the paper's distribution table,
+ * Supplementary A), evaluated on the same skeleton: rgb = c0 + sum w G. The
+ * frame slot is read as for NASGabor; the shape slot holds the family's
+ * values (unused entries are ignored and get zero gradients):
+ *   NASGABOR : (lambda, a, k, zeta), normaliser per `norm` (Section 5.1).
+ *   NASG     : (lambda, a, -, -): NASGabor without carrier (Supplementary E)
+ *              with its exact normaliser lambda sqrt(1+a)/(2 pi (1-e^{-2 lambda}));
+ *              also accepts NASG_PARAM_ANGLES (k and zeta unused).
+ *   SG       : (lambda, -, -, -): lambda/(2 pi (1-e^{-2 lambda})) e^{lambda (z.d-1)}.
+ *   SB       : (beta >= 0, -, -, -): (beta+1)/(2 pi) (z.d)^beta on z.d > 0, else 0
+ *              (the hemisphere normalisation of Supplementary D).
+ *   SC       : (rho in [0, 1), -, -, -):
+ *              1/(4 pi) ((1 - rho^2)/(1 + rho^2 - 2 rho z.d))^2 (the spherical
+ *              Cauchy distribution the table cites; its printed
+ *              "1 - rho^2 - 2 rho z.d" is not a density).
+ *   ASG      : (mu, lambda, -, -): max(z.d, 0) e^{-mu (x.d)^2 - lambda (y.d)^2},
+ *              y = z x x, no normaliser (the table gives none).
+ * SG, SB, SC and ASG take NASG_PARAM_QUAT only; `norm` is validated but used
+ * by NASGabor only. The families other than NASGabor use a fixed lane
+ * mapping by view count (tuning entries set the block size only) and are not
+ * accepted by the persistent batch (NASG_ERR_MODE).                          */
+typedef enum nasg_family {
+  NASG_FAMILY_NASGABOR = 0,
+  NASG_FAMILY_NASG = 1,
+  NASG_FAMILY_SG = 2,
+  NASG_FAMILY_SB = 3,
+  NASG_FAMILY_SC = 4,
+  NASG_FAMILY_ASG = 5
+} nasg_family;
+
 typedef struct nasg_params {
   const void* quat;   /* [K][N][4]  f32 or bf16                               */
   const void* shape;  /* [K][N][4]  f32 or bf16                               */
@@ -127,7 +157,8 @@ typedef struct nasg_params {
   int32_t k;          /* lobes per primitive, 1..NASG_MAX_LOBES               */
   int32_t dtype;      /* nasg_dtype of quat / shape / rgbw                    */
   int32_t param;      /* nasg_param (NASG_ERR_MODE if unknown)                */
-  int32_t reserved;   /* set to 0                                             */
+  int32_t family;     /* nasg_family (NASG_ERR_MODE if unknown or if the
+                         family does not take `param`)                        */
 } nasg_params;
 
 typedef struct nasg_views {

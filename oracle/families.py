@@ -118,13 +118,9 @@ def _frame(quat):
     (dL/dx, dL/dz, their scales) to the quaternion gradient and scale."""
     q = np.asarray(quat, np.float64)
     x, y, z = R.frame_from_quat(q)
-    jx, jz = R.frame_jacobians(q)
 
     def back(gx, gz, sx, sz):
-        g = np.einsum("knci,knc->kni", jx, gx) + np.einsum("knci,knc->kni", jz, gz)
-        sc = (np.einsum("knci,knc->kni", np.abs(jx), sx)
-              + np.einsum("knci,knc->kni", np.abs(jz), sz))
-        return g, sc
+        return R.quat_gradient(q, gx, gz, sx, sz)
     return x, y, z, back
 
 
@@ -203,7 +199,9 @@ def forward_backward(family, quat, shape, rgbw, c0, grad_rgb, means=None, cams=N
           + np.einsum("kvn,knc->vnc", gGa * sza, np.abs(z)))
     proj = np.eye(3)[None, None] - d[..., :, None] * d[..., None, :]
     ge = np.einsum("vnij,vnj->vni", proj, gd) / r[..., None]
-    se = np.einsum("vnij,vnj->vni", np.abs(proj), sd) / r[..., None]
+    # the projection's two terms (identity and d d^T) count as separate
+    # elementary contributions: (|g| + |d| (|d| . |g|)) / |e|
+    se = (sd + np.abs(d) * (np.abs(d) * sd).sum(-1, keepdims=True)) / r[..., None]
     key = "dirs" if dirs is not None else "means"
     out[key] = ge.sum(0)
     scale[key] = se.sum(0)

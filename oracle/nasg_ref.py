@@ -66,17 +66,11 @@ def frame_from_quat(q):
     return ax, ay, az
 
 
-def frame_jacobians(q):
-    """d(x axis)/dq and d(z axis)/dq, each [..., 3, 4], for the frame of q/|q|.
-
-    Chain: axis(q_hat) with q_hat = q/|q|, d q_hat/dq = (I - q_hat q_hat^T)/|q|.
-    """
-    q = np.asarray(q, dtype=np.float64)
-    nrm = np.linalg.norm(q, axis=-1, keepdims=True)
-    qn = q / nrm
+def axis_jacobians(qn):
+    """d(x axis)/d q_hat and d(z axis)/d q_hat, each [..., 3, 4], at a unit
+    quaternion q_hat (rows: axis components; columns: w, x, y, z)."""
     w, x, y, z = qn[..., 0], qn[..., 1], qn[..., 2], qn[..., 3]
     zero = np.zeros_like(w)
-    # rows: axis components; columns: (w, x, y, z) of the unit quaternion
     jx = np.stack([
         np.stack([zero, zero, -4 * y, -4 * z], -1),
         np.stack([2 * z, 2 * y, 2 * x, 2 * w], -1),
@@ -87,9 +81,41 @@ def frame_jacobians(q):
         np.stack([-2 * x, -2 * w, 2 * z, 2 * y], -1),
         np.stack([zero, -4 * x, -4 * y, zero], -1),
     ], -2)
+    return jx, jz
+
+
+def frame_jacobians(q):
+    """d(x axis)/dq and d(z axis)/dq, each [..., 3, 4], for the frame of q/|q|.
+
+    Chain: axis(q_hat) with q_hat = q/|q|, d q_hat/dq = (I - q_hat q_hat^T)/|q|.
+    """
+    q = np.asarray(q, dtype=np.float64)
+    nrm = np.linalg.norm(q, axis=-1, keepdims=True)
+    qn = q / nrm
+    jx, jz = axis_jacobians(qn)
     eye = np.broadcast_to(np.eye(4), q.shape[:-1] + (4, 4))
     proj = (eye - qn[..., :, None] * qn[..., None, :]) / nrm[..., None]
     return jx @ proj, jz @ proj
+
+
+def quat_gradient(q, gx, gz, sx, sz):
+    """dL/dq [..., 4] from dL/dx, dL/dz [..., 3] and its rounding scale, by the
+    chain of ``frame_jacobians`` taken in two steps: v = (d axis/d q_hat)^T
+    dL/daxis, then dL/dq = (v - q_hat (q_hat . v)) / |q|. The scale keeps the
+    two terms of that projection as separate elementary contributions,
+    (|v| + |q_hat| (|q_hat| . |v|)) / |q| with |v| from the absolute terms:
+    a component of dL/dq can be the small difference of two large ones (a lobe
+    that depends on z only, with q near a rotation about a coordinate axis)."""
+    q = np.asarray(q, dtype=np.float64)
+    nrm = np.linalg.norm(q, axis=-1, keepdims=True)
+    qn = q / nrm
+    ux, uz = axis_jacobians(qn)
+    v = np.einsum("...ci,...c->...i", ux, gx) + np.einsum("...ci,...c->...i", uz, gz)
+    va = (np.einsum("...ci,...c->...i", np.abs(ux), sx)
+          + np.einsum("...ci,...c->...i", np.abs(uz), sz))
+    g = (v - qn * (qn * v).sum(-1, keepdims=True)) / nrm
+    sc = (va + np.abs(qn) * (np.abs(qn) * va).sum(-1, keepdims=True)) / nrm
+    return g, sc
 
 
 # --------------------------------------------------------------------- normalisers
@@ -308,11 +334,7 @@ def forward_backward(quat, shape, rgbw, c0, grad_rgb, norm, means=None, cams=Non
     out, scale, axes = frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm,
                                               means, cams, dirs)
     gx_vec, gz_vec, sx_vec, sz_vec = axes
-    jx, jz = frame_jacobians(quat)
-    out["quat"] = (np.einsum("knci,knc->kni", jx, gx_vec)
-                   + np.einsum("knci,knc->kni", jz, gz_vec))
-    scale["quat"] = (np.einsum("knci,knc->kni", np.abs(jx), sx_vec)
-                     + np.einsum("knci,knc->kni", np.abs(jz), sz_vec))
+    out["quat"], scale["quat"] = quat_gradient(quat, gx_vec, gz_vec, sx_vec, sz_vec)
     return out, scale
 
 
@@ -418,7 +440,9 @@ def frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm, means=None, 
           + np.einsum("kvn,knc->vnc", gGa * szva, np.abs(az)))
     proj = np.eye(3)[None, None] - d[..., :, None] * d[..., None, :]
     ge = np.einsum("vnij,vnj->vni", proj, gd) / r[..., None]
-    se = np.einsum("vnij,vnj->vni", np.abs(proj), sd) / r[..., None]
+    # the projection's two terms (identity and d d^T) count as separate
+    # elementary contributions: (|g| + |d| (|d| . |g|)) / |e|
+    se = (sd + np.abs(d) * (np.abs(d) * sd).sum(-1, keepdims=True)) / r[..., None]
     key = "dirs" if dirs is not None else "means"
     out[key] = ge.sum(0)
     scale[key] = se.sum(0)

@@ -16,13 +16,14 @@ NASG_F32, NASG_BF16 = 0, 1
 NORM_EXACT, NORM_APPROX = 0, 1
 GRAD_OVERWRITE, GRAD_ACCUMULATE = 0, 1
 PARAM_QUAT, PARAM_ANGLES = 0, 1
+FAMILIES = {"nasgabor": 0, "nasg": 1, "sg": 2, "sb": 3, "sc": 4, "asg": 5}
 KERNEL_NASG_FWD, KERNEL_NASG_BWD, KERNEL_SH_FWD, KERNEL_SH_BWD = 0, 1, 2, 3
 
 
 class NasgParams(C.Structure):
     _fields_ = [("quat", C.c_void_p), ("shape", C.c_void_p), ("rgbw", C.c_void_p),
                 ("c0", C.c_void_p), ("n", C.c_int64), ("k", C.c_int32), ("dtype", C.c_int32),
-                ("param", C.c_int32), ("reserved", C.c_int32)]
+                ("param", C.c_int32), ("family", C.c_int32)]
 
 
 class NasgViews(C.Structure):

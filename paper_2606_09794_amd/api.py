@@ -8,6 +8,8 @@ tensors in the layouts of ``include/nasg.h``:
     c0 [N][3], means [N][3], cams [V][3] or dirs [N][3], grad_rgb [V][N][3]
     sh [16][3][N]                                       float32
 
+``family`` picks the lobe ("nasgabor" default, or "nasg", "sg", "sb", "sc",
+"asg"; see include/nasg.h for each family's shape values).
 ``param="quat"`` (default) reads quat / shape / rgbw as a quaternion frame,
 (lambda, a, k, zeta) and weights; ``param="angles"`` reads the paper's raw
 pre-activation values in the same slots (frame cosines tanh(u), lambda and a
@@ -79,7 +81,15 @@ def _views(n: int, means, cams, dirs):
     return L.NasgViews(means.data_ptr(), cams.data_ptr(), None, v), v
 
 
-def _params(quat, shape, rgbw, c0, param="quat"):
+def _family_code(family) -> int:
+    if isinstance(family, str):
+        if family not in L.FAMILIES:
+            raise ValueError(f"family must be one of {sorted(L.FAMILIES)}")
+        return L.FAMILIES[family]
+    return int(family)
+
+
+def _params(quat, shape, rgbw, c0, param="quat", family="nasgabor"):
     dt = quat.dtype
     if dt not in (torch.float32, torch.bfloat16):
         raise ValueError("lobe parameters must be float32 or bfloat16")
@@ -93,13 +103,15 @@ def _params(quat, shape, rgbw, c0, param="quat"):
         raise ValueError("expected quat/shape [K][N][4], rgbw [K][3][N], c0 [N][3]")
     code = L.NASG_F32 if dt == torch.float32 else L.NASG_BF16
     return L.NasgParams(quat.data_ptr(), shape.data_ptr(), rgbw.data_ptr(), c0.data_ptr(),
-                        n, k, code, _param_code(param), 0), k, n
+                        n, k, code, _param_code(param), _family_code(family)), k, n
 
 
 def nasg_eval_fwd(quat, shape, rgbw, c0, *, means=None, cams=None, dirs=None, norm="exact",
-                  out: Optional[torch.Tensor] = None, param="quat") -> torch.Tensor:
-    """Per-view colours rgb[V][N][3] (Section 4.2 model with NASGabor lobes)."""
-    p, k, n = _params(quat, shape, rgbw, c0, param)
+                  out: Optional[torch.Tensor] = None, param="quat", family="nasgabor"
+                  ) -> torch.Tensor:
+    """Per-view colours rgb[V][N][3] (Section 4.2 model; NASGabor lobes or
+    another family of the distribution table, ``family``)."""
+    p, k, n = _params(quat, shape, rgbw, c0, param, family)
     vw, v = _views(n, means, cams, dirs)
     if out is None:
         out = torch.empty((v, n, 3), device=quat.device, dtype=torch.float32)
@@ -119,11 +131,11 @@ def nasg_grad_buffers(k: int, n: int, device) -> Dict[str, torch.Tensor]:
 def nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb, *, means=None, cams=None, dirs=None,
                   norm="exact", grads: Optional[Dict[str, torch.Tensor]] = None,
                   accumulate: bool = False, rgb_out: Optional[torch.Tensor] = None,
-                  param="quat") -> Dict[str, torch.Tensor]:
+                  param="quat", family="nasgabor") -> Dict[str, torch.Tensor]:
     """Gradients of sum(grad_rgb * rgb) w.r.t. quat, shape, rgbw, c0 and the
     means (or dirs) as float32 tensors (dict keys quat, shape, rgbw, c0, geom).
     With ``rgb_out`` the forward colours are written in the same pass."""
-    p, k, n = _params(quat, shape, rgbw, c0, param)
+    p, k, n = _params(quat, shape, rgbw, c0, param, family)
     vw, v = _views(n, means, cams, dirs)
     _dev(grad_rgb, "grad_rgb")
     if tuple(grad_rgb.shape) != (v, n, 3):

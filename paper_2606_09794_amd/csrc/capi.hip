@@ -80,6 +80,8 @@ int check_params(const nasg_params* p) {
   if (p->n < 0 || p->k < 1 || p->k > NASG_MAX_LOBES) return NASG_ERR_SHAPE;
   if (p->dtype != NASG_F32 && p->dtype != NASG_BF16) return NASG_ERR_DTYPE;
   if (p->param != NASG_PARAM_QUAT && p->param != NASG_PARAM_ANGLES) return NASG_ERR_MODE;
+  if (p->family < NASG_FAMILY_NASGABOR || p->family > NASG_FAMILY_ASG) return NASG_ERR_MODE;
+  if (p->param == NASG_PARAM_ANGLES && p->family > NASG_FAMILY_NASG) return NASG_ERR_MODE;
   if (p->n == 0) return NASG_OK;  // nothing is read: pointers may be NULL
   if (p->quat == nullptr || p->shape == nullptr || p->rgbw == nullptr || p->c0 == nullptr)
     return NASG_ERR_NULL;
@@ -104,6 +106,7 @@ NasgArgs make_args(const nasg_params* p, const nasg_views* vw) {
   a.k = p->k;
   a.v = vw->v;
   a.param = p->param;
+  a.family = p->family;
   return a;
 }
 
@@ -306,6 +309,7 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
     int st = check_params(&sc.p);
     if (st != NASG_OK) return st;
     if (sc.p.dtype != NASG_F32) return NASG_ERR_DTYPE;
+    if (sc.p.family != NASG_FAMILY_NASGABOR) return NASG_ERR_MODE;
     if ((st = check_views(&sc.views, sc.p.n)) != NASG_OK) return st;
     if (sc.p.n > 0 && (st = check_grad_ptrs(sc.grad_rgb, &sc.g, sc.rgb)) != NASG_OK) return st;
   }

@@ -27,11 +27,28 @@ struct NasgArgs {
   int32_t norm;
   int32_t accumulate;
   int32_t param;       // 0: quaternion + (lam, a, k, zeta); 1: the paper's raw values
-  int32_t pad;
+  int32_t family;      // lobe family (kFam*)
 };
 
 constexpr int kParamQuat = 0;
 constexpr int kParamAngles = 1;
+
+// lobe families (the values of nasg_family)
+constexpr int kFamNasgabor = 0;
+constexpr int kFamNasg = 1;
+constexpr int kFamSg = 2;
+constexpr int kFamSb = 3;
+constexpr int kFamSc = 4;
+constexpr int kFamAsg = 5;
+
+// The lane mappings compiled for the families other than NASGabor, by view
+// count: (1, 1) for V = 1, (2, 2) up to 4, (4, 2) up to 8, (8, 2) above.
+inline void family_mapping(int v, int& lanes, int& vpl) {
+  if (v <= 1) { lanes = 1; vpl = 1; }
+  else if (v <= 4) { lanes = 2; vpl = 2; }
+  else if (v <= 8) { lanes = 4; vpl = 2; }
+  else { lanes = 8; vpl = 2; }
+}
 
 struct ShArgs {
   const float* sh;
@@ -90,6 +107,9 @@ constexpr int kBatchLanes[6] = {1, 2, 8, 1, 2, 8};
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
                           uint32_t* counter, uint64_t token, int grid, hipStream_t s);
+
+// SG, SB, SC and ASG lobes (csrc/family_kernels.hip), lane mapping by view count.
+hipError_t launch_family(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s);
 
 hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
                        hipStream_t s);

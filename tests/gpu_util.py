@@ -3,6 +3,7 @@ the same stored values, compare with the scale-normalised error."""
 import numpy as np
 import torch
 
+from oracle import families as F
 from oracle import metrics as M
 from oracle import nasg_paper as Pp
 from oracle import nasg_ref as R
@@ -31,11 +32,19 @@ def dgeo(d):
     return {"dirs": d["dirs"]} if d["dirs"] is not None else {"means": d["means"], "cams": d["cams"]}
 
 
+FAMILY_CODES = {"nasg": F.NASG, "sg": F.SG, "sb": F.SB, "sc": F.SC, "asg": F.ASG}
+
+
 def oracle_nasg(w, norm):
-    """The oracle for the workload's lobe parametrisation (quaternion or the
-    paper's raw values)."""
-    fb = Pp.forward_backward if getattr(w, "param", "quat") == "angles" else R.forward_backward
-    out, scale = fb(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, NORMS[norm], **geo(w))
+    """The oracle for the workload's lobe family and parametrisation
+    (quaternion or the paper's raw values)."""
+    fam = getattr(w, "family", "nasgabor")
+    if fam != "nasgabor":
+        out, scale = F.forward_backward(FAMILY_CODES[fam], w.quat, w.shape, w.rgbw, w.c0,
+                                        w.grad_rgb, param=w.param, **geo(w))
+    else:
+        fb = Pp.forward_backward if getattr(w, "param", "quat") == "angles" else R.forward_backward
+        out, scale = fb(w.quat, w.shape, w.rgbw, w.c0, w.grad_rgb, NORMS[norm], **geo(w))
     key = "dirs" if w.dirs is not None else "means"
     out["geom"], scale["geom"] = out.pop(key), scale.pop(key)
     return out, scale

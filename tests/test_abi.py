@@ -54,7 +54,8 @@ def fwd(lib, p, v, rgb=FAKE, norm=0):
     (dict(quat=None), -1), (dict(quat=FAKE + 4), -3), (dict(c0=FAKE + 2), -3),
     (dict(v=0), -2), (dict(v=5000), -2), (dict(dirs=FAKE, v=2), -2), (dict(cams=None), -1),
     (dict(rgb=None), -1), (dict(rgb=FAKE + 1), -3), (dict(norm=7), -5),
-    (dict(param=2), -5), (dict(param=-1), -5),
+    (dict(param=2), -5), (dict(param=-1), -5), (dict(family=6), -5), (dict(family=-1), -5),
+    (dict(param=1, family=2), -5), (dict(param=1, family=5), -5),
 ])
 def test_fwd_rejects(lib, case, code):
     case = dict(case)
@@ -141,6 +142,9 @@ def test_batched_rejects(lib):
     sc[0].p.dtype = 1
     assert plan() == -4
     sc[0].p.dtype = 0
+    sc[0].p.family = 2                                   # only NASGabor lobes are batched
+    assert plan() == -5
+    sc[0].p.family = 0
     sc[0].grad_rgb = None
     assert plan() == -1
     assert lib.nasg_batched_run(None, None) == -1

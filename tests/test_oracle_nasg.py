@@ -384,3 +384,20 @@ def test_special_points_gradients_finite():
         assert np.isfinite(v).all()
     assert np.all(out["shape"][0, 1] == 0) and np.all(out["quat"][0, 1] == 0)
     assert np.all(out["dirs"][1] == 0)
+
+
+def test_quat_gradient_two_step_chain():
+    """dL/dq through (d axis/d q_hat)^T then the tangent projection equals the
+    projected Jacobian of frame_jacobians; its scale bounds the scale of the
+    projected Jacobian's absolute terms."""
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal((6, 7, 4))
+    q[0, :, 1:3] *= 1e-3                     # near a rotation about a coordinate axis
+    gx, gz = rng.standard_normal((6, 7, 3)), rng.standard_normal((6, 7, 3))
+    jx, jz = R.frame_jacobians(q)
+    ref = np.einsum("knci,knc->kni", jx, gx) + np.einsum("knci,knc->kni", jz, gz)
+    g, sc = R.quat_gradient(q, gx, gz, np.abs(gx), np.abs(gz))
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-14)
+    old = np.einsum("knci,knc->kni", np.abs(jx), np.abs(gx)) + np.einsum("knci,knc->kni", np.abs(jz), np.abs(gz))
+    assert np.all(sc >= old * (1 - 1e-12))
+

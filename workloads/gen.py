@@ -31,6 +31,13 @@ above), u_k from N(0, 1) (k = 20 (tanh u + 1) spreads over the paper's
 [0, 40]) and zeta = 0 (the paper's carrier); ``rgbw`` holds the weights'
 u from N(0, 0.5^2) (w = tanh u).
 
+With ``family`` other than "nasgabor" the shape slot holds that lobe
+family's values (the distribution table of Supplementary A): "nasg"
+(lambda, a, 0, 0) and "sg" (lambda, 0, 0, 0) with lambda, a log-uniform in
+[1, 1e3]; "sb" (beta, 0, 0, 0) with beta log-uniform in [1, 1e3]; "sc"
+(rho, 0, 0, 0) with rho uniform in [0, 0.95]; "asg" (mu, lambda, 0, 0) both
+log-uniform in [1, 1e3]. Frames, weights and geometry are drawn as above.
+
 Nothing here evaluates the appearance model: the module draws, rounds to the
 storage dtype and gathers, so the oracle and the HIP path consume identical
 stored bits.
@@ -83,6 +90,7 @@ class Workload:
     rgbw_bits: Optional[np.ndarray] = None
     orig: Optional[dict] = None  # float32 values before bf16 rounding
     param: str = "quat"         # "quat" or "angles" (the paper's raw values)
+    family: str = "nasgabor"    # lobe family of the shape slot
 
     @property
     def evals(self) -> int:
@@ -107,6 +115,28 @@ def _draw_lobes(rng: np.random.Generator, k: int, n: int):
     return quat, np.ascontiguousarray(shape), rgbw, c0
 
 
+FAMILIES = ("nasgabor", "nasg", "sg", "sb", "sc", "asg")
+
+
+def _draw_family_lobes(rng: np.random.Generator, k: int, n: int, family: str):
+    quat = rng.standard_normal((k, n, 4), dtype=np.float32)
+    logu = lambda: np.exp(rng.uniform(0.0, math.log(1e3), (k, n))).astype(np.float32)  # noqa: E731
+    z = np.zeros((k, n), np.float32)
+    if family in ("nasg", "asg"):
+        p0 = logu()
+        p1 = logu()
+    elif family in ("sg", "sb"):
+        p0, p1 = logu(), z
+    elif family == "sc":
+        p0, p1 = rng.uniform(0.0, 0.95, (k, n)).astype(np.float32), z
+    else:
+        raise ValueError(f"unknown lobe family {family!r}")
+    shape = np.stack([p0, p1, z, z], axis=-1)
+    rgbw = (0.5 * rng.standard_normal((k, 3, n), dtype=np.float32)).astype(np.float32)
+    c0 = (0.5 * rng.standard_normal((n, 3), dtype=np.float32)).astype(np.float32)
+    return quat, np.ascontiguousarray(shape), rgbw, c0
+
+
 def _draw_paper_lobes(rng: np.random.Generator, k: int, n: int):
     frame = np.zeros((k, n, 4), np.float32)
     frame[..., :3] = rng.standard_normal((k, n, 3), dtype=np.float32)
@@ -126,11 +156,14 @@ def _draw_cams(rng: np.random.Generator, v: int) -> np.ndarray:
 
 def draw_workload(seed: int, n: int, k: int, v: int, *, dirs_mode: bool = False,
                   with_grad: bool = True, with_sh: bool = True, dtype: str = "f32",
-                  rng: Optional[np.random.Generator] = None, param: str = "quat") -> Workload:
+                  rng: Optional[np.random.Generator] = None, param: str = "quat",
+                  family: str = "nasgabor") -> Workload:
     """Draw one workload. Order of draws: lobes, diffuse colour, geometry,
     upstream gradient, SH coefficients."""
     rng = np.random.default_rng(seed) if rng is None else rng
-    if param == "quat":
+    if family != "nasgabor" and param == "quat":
+        quat, shape, rgbw, c0 = _draw_family_lobes(rng, k, n, family)
+    elif param == "quat":
         quat, shape, rgbw, c0 = _draw_lobes(rng, k, n)
     elif param == "angles":
         quat, shape, rgbw, c0 = _draw_paper_lobes(rng, k, n)
@@ -147,7 +180,7 @@ def draw_workload(seed: int, n: int, k: int, v: int, *, dirs_mode: bool = False,
     grad_rgb = rng.standard_normal((v, n, 3), dtype=np.float32) if with_grad else None
     sh = (0.3 * rng.standard_normal((16, 3, n), dtype=np.float32)).astype(np.float32) if with_sh else None
     w = Workload(n=n, k=k, v=v, quat=quat, shape=shape, rgbw=rgbw, c0=c0, means=means,
-                 cams=cams, dirs=dirs, grad_rgb=grad_rgb, sh=sh, param=param)
+                 cams=cams, dirs=dirs, grad_rgb=grad_rgb, sh=sh, param=param, family=family)
     if dtype == "bf16":
         w.orig = {"quat": quat, "shape": shape, "rgbw": rgbw}
         w.quat_bits = f32_to_bf16_bits(quat)
@@ -214,7 +247,7 @@ def take_primitives(w: Workload, idx: np.ndarray) -> Workload:
         dirs=None if w.dirs is None else np.ascontiguousarray(w.dirs[idx]),
         grad_rgb=None if w.grad_rgb is None else np.ascontiguousarray(w.grad_rgb[:, idx]),
         sh=None if w.sh is None else np.ascontiguousarray(w.sh[:, :, idx]),
-        dtype=w.dtype, param=w.param,
+        dtype=w.dtype, param=w.param, family=w.family,
     )
     if w.dtype == "bf16":
         sub.quat_bits = np.ascontiguousarray(w.quat_bits[:, idx])
