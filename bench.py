@@ -183,10 +183,16 @@ def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
     idx = np.sort(np.random.default_rng(seed).choice(w.n, size=min(n_sample, w.n), replace=False))
     sub = W.take_primitives(w, idx)
     src = sub.orig if orig else {"quat": sub.quat, "shape": sub.shape, "rgbw": sub.rgbw}
-    fb = Pp.forward_backward if w.param == "angles" else R.forward_backward
-    ref, scale = fb(src["quat"], src["shape"], src["rgbw"], sub.c0, sub.grad_rgb,
-                    R.NORM_EXACT if norm == "exact" else R.NORM_APPROX,
-                    means=sub.means, cams=sub.cams)
+    if w.family != "nasgabor":
+        from oracle import families as F
+        code = {"nasg": F.NASG, "sg": F.SG, "sb": F.SB, "sc": F.SC, "asg": F.ASG}[w.family]
+        ref, scale = F.forward_backward(code, src["quat"], src["shape"], src["rgbw"], sub.c0,
+                                        sub.grad_rgb, means=sub.means, cams=sub.cams, param=w.param)
+    else:
+        fb = Pp.forward_backward if w.param == "angles" else R.forward_backward
+        ref, scale = fb(src["quat"], src["shape"], src["rgbw"], sub.c0, sub.grad_rgb,
+                        R.NORM_EXACT if norm == "exact" else R.NORM_APPROX,
+                        means=sub.means, cams=sub.cams)
     ref["geom"], scale["geom"] = ref.pop("means"), scale.pop("means")
     sel = {"rgb": lambda t: t[:, idx], "quat": lambda t: t[:, idx], "shape": lambda t: t[:, idx],
            "rgbw": lambda t: t[:, :, idx], "c0": lambda t: t[idx], "geom": lambda t: t[idx]}
@@ -293,6 +299,38 @@ def bench_other(args, log):
                    compare={"quaternion_parametrisation_same_sizes": {
                        "ms": round(msq, 4), "G_evals_s": round(n * v / msq / 1e6, 4)}},
                    parity_sampled_max_scaled_error=par)
+    elif args.workload == "families":
+        per = {}
+        n, k, v = args.n, 8, args.views
+        ab = algorithmic_bytes(n, k, v)
+        g = P.nasg_grad_buffers(k, n, "cuda")
+        rgb = torch.empty((v, n, 3), device="cuda")
+        for fam in ("nasgabor", "nasg", "sg", "sb", "sc", "asg"):
+            t0 = time.perf_counter()
+            w = W.draw_workload(11, n, k, v, with_sh=False, family=fam)
+            log(f"generated {fam} N={n} K={k} V={v} in {time.perf_counter() - t0:.1f}s")
+            d = upload(w)
+            fn = lambda: P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"],  # noqa: E731
+                                         d["grad_rgb"], means=d["means"], cams=d["cams"],
+                                         norm=args.norm, grads=g, rgb_out=rgb, family=fam)
+            ms = time_launches(fn, args.steps, args.warmup)
+            fn()
+            torch.cuda.synchronize()
+            per[fam] = {"ms": round(ms, 4), "G_evals_s": round(n * v / ms / 1e6, 4),
+                        "hbm_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+                        "parity_sampled_max_scaled_error": _sampled(w, dict(g, rgb=rgb), args.norm,
+                                                                    n_sample=128)}
+            del d
+        best = per["nasgabor"]
+        res.update(value=best["G_evals_s"], ms_per_step=best["ms"], dtype="f32",
+                   config={"workload": f"lobe families of the distribution table, K={k} fused fwd+bwd, "
+                                       f"{n} primitives x {v} cameras each, FP32; value = NASGabor",
+                           "primitives": n, "lobes": k, "views": v},
+                   roofline={"bound": "hbm", "achieved": round(ab / best["ms"] / 1e6, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(ab / best["ms"] / 1e6 / HBM_PEAK_GBS, 4), "traffic": None,
+                             "algorithmic_bytes_per_launch": ab},
+                   families=per)
     elif args.workload == "uneven-batch":
         t0 = time.perf_counter()
         scenes = W.config4()
@@ -377,11 +415,12 @@ def main():
                          "device copy of --copy-mib MiB for calibrating byte counters")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params"],
+                    choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params",
+                             "families"],
                     help="headline: K=8, 3 M primitives x 16 cameras; single-camera: K=8, 1 M x 1; "
                          "bf16-k16: K=16, 6 M x 8, bf16 storage; uneven-batch: 32 scenes in one "
                          "persistent launch; paper-params: the headline sizes with the paper's raw "
-                         "lobe values")
+                         "lobe values; families: every lobe family at the headline sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the path shards by primitive with no "
