@@ -29,9 +29,10 @@
  *   an error nothing is launched and no output is touched.
  * - n == 0 is valid and launches nothing.
  * - Every output is fully overwritten (NASG_GRAD_OVERWRITE) or added to
- *   (NASG_GRAD_ACCUMULATE, gradients only). Results are bitwise
+ *   (NASG_GRAD_ACCUMULATE, gradients only). Appearance results are bitwise
  *   deterministic run to run: per-primitive sums over views are reduced in a
- *   fixed order in registers and wavefront lanes, without atomics.
+ *   fixed order in registers and wavefront lanes, without atomics. (The
+ *   compositing backward at the end of this header is the one exception.)
  *
  * Layouts (primitive index fastest inside each lobe; K lobes lobe-major)
  * ---------------------------------------------------------------------
@@ -90,13 +91,16 @@ typedef enum nasg_status {
   NASG_OK = 0,
   NASG_ERR_NULL = -1,      /* a required pointer is NULL                      */
   NASG_ERR_SHAPE = -2,     /* n < 0, k outside [1, NASG_MAX_LOBES], v outside
-                              [1, NASG_MAX_VIEWS], or dirs given with v != 1  */
+                              [1, NASG_MAX_VIEWS], dirs given with v != 1, or
+                              compositing: image side or tile capacity out of
+                              range, n >= 2^31                                */
   NASG_ERR_ALIGN = -3,     /* a pointer is not aligned as the layout requires */
   NASG_ERR_DTYPE = -4,     /* unknown storage dtype                           */
   NASG_ERR_MODE = -5,      /* unknown normaliser, gradient mode, lobe
                               parametrisation or lobe family                  */
   NASG_ERR_LAUNCH = -6,    /* the HIP runtime rejected a launch               */
-  NASG_ERR_WORKSPACE = -7  /* batched: workspace missing, too small or stale  */
+  NASG_ERR_WORKSPACE = -7  /* batched or compositing: workspace too small, or
+                              (batched) missing or stale                      */
 } nasg_status;
 
 enum { NASG_MAX_LOBES = 64, NASG_MAX_VIEWS = 4096 };
@@ -265,6 +269,79 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
 /* Run a plan: one queue-reset kernel and one persistent kernel on `stream`.
  * No allocation, copy or synchronisation: capturable into a hipGraph.       */
 int nasg_batched_run(const nasg_batch* b, void* stream);
+
+/* ---- compositing into an image (Section 3.1) ------------------------------
+ * C(pixel) = sum_i T_i alpha_i c_i over the primitives on the pixel's ray in
+ * depth order, alpha_i = min(sigma_i rho_i, 0.99), T_i = prod_{j<i}(1 -
+ * alpha_j), black background, no early termination. Each primitive is a 3D
+ * Gaussian, Sigma = R S S^T R^T (Section 3.1's primitive), and rho_i is the
+ * Gaussian projected onto the image plane by the local affine approximation
+ * of the perspective map at its mean, evaluated at the pixel centre
+ * (px + 1/2, py + 1/2):
+ *   x_cam = R_cw x + t; u = fx X/Z + cx, v = fy Y/Z + cy;
+ *   Sigma_2 = J R_cw Sigma R_cw^T J^T, J = [[fx/Z, 0, -fx X/Z^2],
+ *                                         [0, fy/Z, -fy Y/Z^2]];
+ *   rho = exp(-q/2), q = delta^T Sigma_2^{-1} delta, delta = centre - (u, v).
+ * A primitive reaches a pixel only where q <= 9 and only if Z > 0.2; depth
+ * order is by Z of the mean, ties by primitive index. The colours are any
+ * per-primitive RGB, typically one view's rgb from nasg_eval_fwd (the
+ * central-ray colour of Section 5.2), so that the backward's grad_colors is
+ * the grad_rgb of nasg_eval_bwd for that view.
+ *
+ * Work is binned into 16 x 16-pixel tiles. Each tile keeps at most
+ * `tile_capacity` (1..NASG_MAX_TILE_CAPACITY) primitives; when a tile
+ * overflows, the extra primitives are dropped from it and the int32 at byte
+ * offset 0 of the workspace is set nonzero (read it after the forward to
+ * detect an incomplete image). All pointers are device pointers; nothing is
+ * allocated, copied or synchronised, so both calls can be captured. */
+enum { NASG_MAX_TILE_CAPACITY = 4096, NASG_MAX_IMAGE_SIDE = 32768 };
+
+typedef struct nasg_camera {
+  double rot[9];      /* world-to-camera rotation R_cw, row-major             */
+  double t[3];        /* x_cam = R_cw x + t                                   */
+  double fx, fy, cx, cy;
+  int32_t width, height; /* pixels, 1..NASG_MAX_IMAGE_SIDE                    */
+} nasg_camera;
+
+typedef struct nasg_gaussians {
+  const float* means;   /* [N][3]                                             */
+  const float* scales;  /* [N][3] per-axis standard deviations (> 0)          */
+  const float* rots;    /* [N][4] quaternion (w, x, y, z), any nonzero norm   */
+  const float* opac;    /* [N]    sigma in [0, 1]                             */
+  const float* colors;  /* [N][3] colour composited for this camera           */
+  int64_t n;            /* 0..2^31-1 (n == 0 still writes a black image)      */
+} nasg_gaussians;
+
+/* Device bytes of the workspace for n primitives, this camera and capacity
+ * (0 for invalid arguments). Layout, each part 256-byte aligned: header
+ * (int32 overflow flag at offset 0), tile cursors [tiles] int32, tile lists
+ * [tiles][capacity] int32, projection records [N] (64 B each), the final
+ * transmittance per pixel [H][W][2] FP64 (mantissa, power-of-two exponent)
+ * and the FP64 gradient accumulators [N][4]. The workspace must be 256-byte
+ * aligned. */
+size_t nasg_raster_workspace_bytes(int64_t n, const nasg_camera* cam, int32_t tile_capacity);
+
+/* Forward: image[H][W][3] (float32, every pixel written; transmittance and
+ * colour sums are carried in FP64, rho in FP32). Leaves the projection, the
+ * depth-sorted tile lists and each pixel's final transmittance in
+ * `workspace` for the backward. */
+int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
+                    void* workspace, size_t ws_bytes, float* image, void* stream);
+
+/* Backward of L = sum grad_image * image with respect to the colours
+ * (grad_colors [N][3]) and the opacities (grad_opac [N]); either may be NULL,
+ * both are overwritten. dC/dc_i = alpha_i T_i; dC/dalpha_i = T_i c_i - S_i /
+ * (1 - alpha_i) with S_i the colour composited behind i, evaluated back to
+ * front as T_i (c_i - R_{i+1}), R_k = alpha_k c_k + (1 - alpha_k) R_{k+1};
+ * dalpha/dsigma = rho below the clamp, 0 at it. Means, scales and rotations get no gradient here.
+ * `workspace` must hold the forward's state for the same inputs and camera
+ * (the backward overwrites only its accumulator part, so it may be repeated).
+ * Per-pixel terms are summed per wavefront in registers and then into FP64
+ * per-primitive accumulators with atomics, so the float32 results are
+ * reproducible up to the order of those FP64 additions. */
+int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
+                    void* workspace, size_t ws_bytes, const float* grad_image,
+                    float* grad_colors, float* grad_opac, void* stream);
 
 /* Human-readable name of a status code (static storage).                    */
 const char* nasg_status_string(int status);

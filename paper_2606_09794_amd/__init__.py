@@ -5,6 +5,7 @@ The compute path is libnasg.so (hand-written HIP for gfx950, C ABI in
 ``python -m paper_2606_09794_amd.build``.
 """
 from .api import (  # noqa: F401
+    Camera,
     NasgBatchPlan,
     NasgEval,
     SH3Eval,
@@ -12,6 +13,11 @@ from .api import (  # noqa: F401
     nasg_eval_bwd,
     nasg_eval_fwd,
     nasg_grad_buffers,
+    raster_bwd,
+    raster_fwd,
+    raster_workspace_bytes,
+    Rasterize,
+    render_view,
     set_tuning,
     sh3_eval_bwd,
     sh3_eval_fwd,

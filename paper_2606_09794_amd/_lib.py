@@ -55,6 +55,17 @@ class NasgTuning(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("views_per_lane", C.c_int32), ("block", C.c_int32)]
 
 
+class NasgCamera(C.Structure):
+    _fields_ = [("rot", C.c_double * 9), ("t", C.c_double * 3), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class NasgGaussians(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("rots", C.c_void_p),
+                ("opac", C.c_void_p), ("colors", C.c_void_p), ("n", C.c_int64)]
+
+
 EXPORTS = {
     "nasg_eval_fwd": (C.c_int, [C.POINTER(NasgParams), C.POINTER(NasgViews), C.c_void_p,
                                 C.c_int32, C.c_void_p]),
@@ -71,6 +82,12 @@ EXPORTS = {
                                     C.POINTER(NasgBatchTuning), C.c_void_p, C.c_size_t,
                                     C.POINTER(NasgBatch), C.c_void_p]),
     "nasg_batched_run": (C.c_int, [C.POINTER(NasgBatch), C.c_void_p]),
+    "nasg_raster_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(NasgCamera), C.c_int32]),
+    "nasg_raster_fwd": (C.c_int, [C.POINTER(NasgGaussians), C.POINTER(NasgCamera), C.c_int32,
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "nasg_raster_bwd": (C.c_int, [C.POINTER(NasgGaussians), C.POINTER(NasgCamera), C.c_int32,
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "nasg_status_string": (C.c_char_p, [C.c_int]),
     "nasg_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(NasgTuning)]),

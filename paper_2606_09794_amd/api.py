@@ -292,3 +292,116 @@ class SH3Eval(torch.autograd.Function):
         gm = g["geom"] if dirs is None else None
         gd = g["geom"] if dirs is not None else None
         return g["sh"], gm, None, gd
+
+
+# ------------------------------------------------------------- compositing
+
+class Camera:
+    """Pinhole camera for compositing: x_cam = rot @ x + t (rot = world-to-
+    camera rotation), pixel u = fx X/Z + cx, v = fy Y/Z + cy."""
+
+    def __init__(self, rot, t, fx, fy, cx, cy, width, height):
+        self.rot = [float(x) for x in torch.as_tensor(rot, dtype=torch.float64).reshape(9)]
+        self.t = [float(x) for x in torch.as_tensor(t, dtype=torch.float64).reshape(3)]
+        self.fx, self.fy, self.cx, self.cy = float(fx), float(fy), float(cx), float(cy)
+        self.width, self.height = int(width), int(height)
+
+    def struct(self) -> L.NasgCamera:
+        c = L.NasgCamera()
+        c.rot[:] = self.rot
+        c.t[:] = self.t
+        c.fx, c.fy, c.cx, c.cy = self.fx, self.fy, self.cx, self.cy
+        c.width, c.height = self.width, self.height
+        return c
+
+    def centre(self, device) -> torch.Tensor:
+        """Camera centre o = -rot^T t as a [1][3] float32 device tensor (the
+        view input of the appearance evaluation)."""
+        r = torch.tensor(self.rot, dtype=torch.float64).reshape(3, 3)
+        o = -(r.T @ torch.tensor(self.t, dtype=torch.float64))
+        return o.to(torch.float32).reshape(1, 3).to(device)
+
+
+def _gaussians(means, scales, rots, opac, colors) -> L.NasgGaussians:
+    n = means.shape[0]
+    for t, name, shape in ((means, "means", (n, 3)), (scales, "scales", (n, 3)),
+                           (rots, "rots", (n, 4)), (opac, "opac", (n,)),
+                           (colors, "colors", (n, 3))):
+        _dev(t, name)
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    return L.NasgGaussians(_p(means), _p(scales), _p(rots), _p(opac), _p(colors), n)
+
+
+def raster_workspace_bytes(n: int, cam: Camera, tile_capacity: int = 1024) -> int:
+    b = L.lib().nasg_raster_workspace_bytes(n, C.byref(cam.struct()), tile_capacity)
+    if b == 0:
+        raise ValueError("invalid compositing size (n, image side or tile capacity)")
+    return int(b)
+
+
+def raster_fwd(means, scales, rots, opac, colors, cam: Camera, tile_capacity: int = 1024,
+               workspace: Optional[torch.Tensor] = None, check_overflow: bool = True):
+    """image [H][W][3] and the workspace the backward needs. With
+    check_overflow the call waits for the device and raises if a tile list
+    overflowed (the image would miss primitives)."""
+    g = _gaussians(means, scales, rots, opac, colors)
+    cs = cam.struct()
+    nb = raster_workspace_bytes(g.n, cam, tile_capacity)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=means.device)
+    img = torch.empty(cam.height, cam.width, 3, dtype=torch.float32, device=means.device)
+    L.check(L.lib().nasg_raster_fwd(C.byref(g), C.byref(cs), tile_capacity,
+                                    _p(workspace), workspace.numel(), _p(img), _stream()),
+            "nasg_raster_fwd")
+    if check_overflow and int(workspace[:4].view(torch.int32).item()) != 0:
+        raise L.NasgError(f"a tile holds more than {tile_capacity} primitives; "
+                          "raise tile_capacity")
+    return img, workspace
+
+
+def raster_bwd(means, scales, rots, opac, colors, cam: Camera, workspace, grad_image,
+               tile_capacity: int = 1024):
+    """(grad_colors [N][3], grad_opac [N]) of L = sum(grad_image * image),
+    with the workspace of the forward on the same inputs."""
+    g = _gaussians(means, scales, rots, opac, colors)
+    cs = cam.struct()
+    _dev(grad_image, "grad_image")
+    gc = torch.empty_like(colors)
+    go = torch.empty_like(opac)
+    L.check(L.lib().nasg_raster_bwd(C.byref(g), C.byref(cs), tile_capacity, _p(workspace),
+                                    workspace.numel(), _p(grad_image), _p(gc), _p(go),
+                                    _stream()), "nasg_raster_bwd")
+    return gc, go
+
+
+class Rasterize(torch.autograd.Function):
+    """image = Rasterize.apply(means, scales, rots, opac, colors, cam,
+    tile_capacity). Gradients flow to opac and colors (the colours carry them
+    on to the appearance model); means, scales and rots get none here."""
+
+    @staticmethod
+    def forward(ctx, means, scales, rots, opac, colors, cam, tile_capacity=1024):
+        img, ws = raster_fwd(means, scales, rots, opac, colors, cam, tile_capacity)
+        ctx.save_for_backward(means, scales, rots, opac, colors, ws)
+        ctx.cam = cam
+        ctx.cap = tile_capacity
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        means, scales, rots, opac, colors, ws = ctx.saved_tensors
+        gc, go = raster_bwd(means, scales, rots, opac, colors, ctx.cam, ws,
+                            grad_image.contiguous(), ctx.cap)
+        return None, None, None, go, gc, None, None
+
+
+def render_view(quat, shape, rgbw, c0, means, scales, rots, opac, cam: Camera, *,
+                norm="exact", param="quat", tile_capacity=1024):
+    """One training view: the central-ray colour of every primitive for this
+    camera (one appearance evaluation per primitive, Section 5.2), composited
+    into the image (Section 3.1). Differentiable in the lobe parameters, c0,
+    the means (through the view direction) and the opacities."""
+    rgb = NasgEval.apply(quat, shape, rgbw, c0, means, cam.centre(means.device), None, norm,
+                         param)
+    return Rasterize.apply(means, scales, rots, opac, rgb[0], cam, tile_capacity)

@@ -13,6 +13,7 @@
 
 #include "../../include/nasg.h"
 #include "nasg_launch.hpp"
+#include "raster.hpp"
 
 namespace {
 
@@ -146,6 +147,75 @@ BatchLayout batch_layout(const nasg_scene* sc, int32_t n, int32_t tile_iters) {
 
 nasg_batch_tuning batch_defaults(const nasg_batch_tuning* t) {
   return t ? *t : nasg_batch_tuning{4, 2};
+}
+
+// ---- compositing
+struct RasterLayout {
+  int32_t tiles_x, tiles_y;
+  size_t cursor_off, lists_off, proj_off, image_off, acc_off, total;
+};
+
+bool raster_layout(int64_t n, const nasg_camera* cam, int32_t cap, RasterLayout* L) {
+  if (cam == nullptr || n < 0 || n > INT32_MAX || cap < 1 || cap > NASG_MAX_TILE_CAPACITY ||
+      cam->width < 1 || cam->height < 1 || cam->width > NASG_MAX_IMAGE_SIDE ||
+      cam->height > NASG_MAX_IMAGE_SIDE)
+    return false;
+  L->tiles_x = (cam->width + nasg::kTile - 1) / nasg::kTile;
+  L->tiles_y = (cam->height + nasg::kTile - 1) / nasg::kTile;
+  const size_t tiles = static_cast<size_t>(L->tiles_x) * L->tiles_y;
+  L->cursor_off = 256;
+  L->lists_off = align_up(L->cursor_off + 4 * tiles, 256);
+  L->proj_off = align_up(L->lists_off + 4 * tiles * static_cast<size_t>(cap), 256);
+  L->image_off = align_up(L->proj_off + sizeof(nasg::ProjRec) * static_cast<size_t>(n), 256);
+  L->acc_off = align_up(L->image_off + 2 * sizeof(double) * static_cast<size_t>(cam->width) *
+                                           static_cast<size_t>(cam->height),
+                        256);
+  L->total = L->acc_off + 4 * sizeof(double) * static_cast<size_t>(n);
+  return true;
+}
+
+int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, const void* ws,
+                size_t ws_bytes, nasg::RasterArgs* a) {
+  if (g == nullptr || cam == nullptr) return NASG_ERR_NULL;
+  RasterLayout L{};
+  if (!raster_layout(g->n, cam, cap, &L)) return NASG_ERR_SHAPE;
+  if (ws == nullptr) return NASG_ERR_NULL;
+  if (ws_bytes < L.total) return NASG_ERR_WORKSPACE;
+  if (!aligned(ws, 256)) return NASG_ERR_ALIGN;
+  if (g->n > 0) {
+    if (!g->means || !g->scales || !g->rots || !g->opac || !g->colors) return NASG_ERR_NULL;
+    if (!aligned(g->means, 4) || !aligned(g->scales, 4) || !aligned(g->rots, 4) ||
+        !aligned(g->opac, 4) || !aligned(g->colors, 4))
+      return NASG_ERR_ALIGN;
+  }
+  *a = nasg::RasterArgs{};
+  a->means = g->means;
+  a->scales = g->scales;
+  a->rots = g->rots;
+  a->opac = g->opac;
+  a->colors = g->colors;
+  a->n = g->n;
+  for (int i = 0; i < 9; ++i) a->cam_rot[i] = cam->rot[i];
+  for (int i = 0; i < 3; ++i) a->cam_t[i] = cam->t[i];
+  a->fx = cam->fx;
+  a->fy = cam->fy;
+  a->cx = cam->cx;
+  a->cy = cam->cy;
+  a->width = cam->width;
+  a->height = cam->height;
+  a->tiles_x = L.tiles_x;
+  a->tiles_y = L.tiles_y;
+  a->cap = cap;
+  a->cap_pow2 = 1;
+  while (a->cap_pow2 < cap) a->cap_pow2 <<= 1;
+  unsigned char* base = static_cast<unsigned char*>(const_cast<void*>(ws));
+  a->overflow = reinterpret_cast<int32_t*>(base);
+  a->cursor = reinterpret_cast<int32_t*>(base + L.cursor_off);
+  a->lists = reinterpret_cast<int32_t*>(base + L.lists_off);
+  a->proj = reinterpret_cast<nasg::ProjRec*>(base + L.proj_off);
+  a->pix_state = reinterpret_cast<double*>(base + L.image_off);
+  a->grad_acc = reinterpret_cast<double*>(base + L.acc_off);
+  return NASG_OK;
 }
 
 }  // namespace
@@ -394,6 +464,42 @@ int nasg_batched_run(const nasg_batch* b, void* stream) {
   const hipError_t e = nasg::launch_batched(hdr, scenes, items, &hdr->counter, b->token, b->grid,
                                             static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
+}
+
+size_t nasg_raster_workspace_bytes(int64_t n, const nasg_camera* cam, int32_t tile_capacity) {
+  RasterLayout L{};
+  return raster_layout(n, cam, tile_capacity, &L) ? L.total : 0;
+}
+
+int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
+                    void* workspace, size_t ws_bytes, float* image, void* stream) {
+  nasg::RasterArgs a{};
+  const int st = raster_args(g, cam, tile_capacity, workspace, ws_bytes, &a);
+  if (st != NASG_OK) return st;
+  if (image == nullptr) return NASG_ERR_NULL;
+  if (!aligned(image, 4)) return NASG_ERR_ALIGN;
+  a.image_out = image;
+  return nasg::launch_raster(a, false, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? NASG_OK
+             : NASG_ERR_LAUNCH;
+}
+
+int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
+                    void* workspace, size_t ws_bytes, const float* grad_image,
+                    float* grad_colors, float* grad_opac, void* stream) {
+  nasg::RasterArgs a{};
+  const int st = raster_args(g, cam, tile_capacity, workspace, ws_bytes, &a);
+  if (st != NASG_OK) return st;
+  if (grad_image == nullptr) return NASG_ERR_NULL;
+  if (!aligned(grad_image, 4) || (grad_colors && !aligned(grad_colors, 4)) ||
+      (grad_opac && !aligned(grad_opac, 4)))
+    return NASG_ERR_ALIGN;
+  a.grad_image = grad_image;
+  a.grad_colors = grad_colors;
+  a.grad_opac = grad_opac;
+  return nasg::launch_raster(a, true, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? NASG_OK
+             : NASG_ERR_LAUNCH;
 }
 
 }  // extern "C"

@@ -155,3 +155,41 @@ def test_batched_rejects(lib):
     sc[0].grad_rgb = FAKE
     sc[0].p.n = 512 * 3 + 1
     assert lib.nasg_batched_workspace_bytes(sc, 1, C.byref(t)) == need + 3 * 16
+
+
+def test_raster_rejects(lib):
+    cam = L.NasgCamera((C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1), (C.c_double * 3)(0, 0, 0),
+                       100.0, 100.0, 32.0, 24.0, 64, 48)
+    need = lib.nasg_raster_workspace_bytes(10, C.byref(cam), 256)
+    # 4 x 3 tiles: header, cursors, lists [12][256], 64-byte records, per-pixel
+    # FP64 (t, E), FP64 accumulators, each part 256-byte aligned
+    assert need == 256 + 256 + 12 * 256 * 4 + 768 + 64 * 48 * 2 * 8 + 10 * 32
+    assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 0) == 0
+    assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 4097) == 0
+    assert lib.nasg_raster_workspace_bytes(-1, C.byref(cam), 256) == 0
+    assert lib.nasg_raster_workspace_bytes(10, None, 256) == 0
+    g = L.NasgGaussians(FAKE, FAKE, FAKE, FAKE, FAKE, 10)
+    fwd = lambda gg=C.byref(g), cc=C.byref(cam), cap=256, ws=FAKE, nb=need, img=FAKE: \
+        lib.nasg_raster_fwd(gg, cc, cap, ws, nb, img, None)  # noqa: E731
+    assert fwd(gg=None) == -1
+    assert fwd(cc=None) == -1
+    assert fwd(cap=0) == -2
+    assert fwd(ws=None) == -1
+    assert fwd(nb=need - 1) == -7
+    assert fwd(ws=FAKE + 64) == -3
+    assert fwd(img=None) == -1
+    assert fwd(img=FAKE + 2) == -3
+    bad = L.NasgCamera(cam.rot, cam.t, 1.0, 1.0, 0.0, 0.0, 0, 48)
+    assert fwd(cc=C.byref(bad)) == -2
+    g.opac = None
+    assert fwd() == -1
+    g.opac = FAKE
+    g.rots = FAKE + 1
+    assert fwd() == -3
+    g.rots = FAKE
+    bwd = lambda nb=need, gi=FAKE, gc=FAKE, go=FAKE: lib.nasg_raster_bwd(  # noqa: E731
+        C.byref(g), C.byref(cam), 256, FAKE, nb, gi, gc, go, None)
+    assert bwd(gi=None) == -1
+    assert bwd(nb=need - 8) == -7
+    assert bwd(gc=FAKE + 1) == -3
+    assert bwd(go=FAKE + 2) == -3

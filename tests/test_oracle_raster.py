@@ -102,3 +102,35 @@ def test_image_is_linear_in_colours():
     a = RR.render(means, scales, rots, opac, colors, CAM)[0]["image"]
     b = RR.render(means, scales, rots, opac, 2 * colors, CAM)[0]["image"]
     np.testing.assert_allclose(b, 2 * a, rtol=1e-14, atol=1e-15)
+
+
+def test_window_render_matches_crop():
+    """Rendering a window with the principal point shifted by the window's
+    corner, over only the primitives whose 3-sigma box meets the window,
+    reproduces that window of the full render (used to check large images on
+    windows)."""
+    import workloads as W
+    sc = W.draw_splat_scene(11, 600, 80, 60, scale=(0.05, 0.5))
+    full, fs = RR.render(sc.means, sc.scales, sc.rots, sc.opac, sc.colors, sc.cam,
+                         grad_image=sc.grad_image)
+    x0, y0, w, h = 50, 37, 30, 23
+    g = np.zeros_like(sc.grad_image)
+    g[y0:y0 + h, x0:x0 + w] = sc.grad_image[y0:y0 + h, x0:x0 + w]
+    masked, _ = RR.render(sc.means, sc.scales, sc.rots, sc.opac, sc.colors, sc.cam, grad_image=g)
+    p = RR.project(sc.means, sc.scales, sc.rots, sc.cam)
+    ex = 3 * np.sqrt(p["cov2"][:, 0, 0]) + 1
+    ey = 3 * np.sqrt(p["cov2"][:, 1, 1]) + 1
+    keep = p["vis"] & (p["u"] + ex >= x0) & (p["u"] - ex <= x0 + w) & \
+        (p["v"] + ey >= y0) & (p["v"] - ey <= y0 + h)
+    idx = np.nonzero(keep)[0]
+    assert 0 < len(idx) < 600
+    cam = dict(sc.cam, cx=sc.cam["cx"] - x0, cy=sc.cam["cy"] - y0, width=w, height=h)
+    win, _ = RR.render(sc.means[idx], sc.scales[idx], sc.rots[idx], sc.opac[idx], sc.colors[idx],
+                       cam, grad_image=sc.grad_image[y0:y0 + h, x0:x0 + w])
+    np.testing.assert_allclose(win["image"], full["image"][y0:y0 + h, x0:x0 + w], rtol=1e-12,
+                               atol=1e-14)
+    np.testing.assert_allclose(win["colors"], masked["colors"][idx], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(win["opac"], masked["opac"][idx], rtol=1e-11, atol=1e-13)
+    rest = np.ones(600, bool)
+    rest[idx] = False
+    assert np.all(masked["colors"][rest] == 0) and np.all(masked["opac"][rest] == 0)

@@ -17,3 +17,4 @@ from .gen import (  # noqa: F401
     bf16_bits_to_f32,
     take_primitives,
 )
+from .raster import SplatScene, draw_splat_scene  # noqa: F401
