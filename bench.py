@@ -394,9 +394,118 @@ def bench_other(args, log):
                                                    "G_evals_s": round(evals / ms_sep / 1e6, 4)},
                             "tuner_sweep_ms": {f"tile{t_}_bpc{b_}": round(m_, 4) for m_, t_, b_ in sweep}},
                    parity_sampled_max_scaled_error=worst)
+    elif args.workload == "training-view":
+        res.update(_training_view(args, log))
     else:
         raise SystemExit(f"unknown workload {args.workload}")
     print(json.dumps(res), flush=True)
+
+
+def _training_view(args, log):
+    """One training view: NASGabor colours of every primitive along its
+    central ray for one camera, compositing into a 1920 x 1080 image,
+    the compositing backward and the appearance backward on its colour
+    gradients. One step = those four calls."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    from oracle import metrics as M
+    from oracle import nasg_ref as R
+    from oracle import raster_ref as RR
+    n, k, width, height, cap = args.n, 8, 1920, 1080, 4096
+    t0 = time.perf_counter()
+    sc = W.draw_splat_scene(12, n, width, height)
+    w = W.draw_workload(12, n, k, 1, with_grad=False, with_sh=False)
+    log(f"generated scene N={n} {width}x{height}, K={k} lobes in {time.perf_counter() - t0:.1f}s")
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    means, scales, rots, opac = dv(sc.means), dv(sc.scales), dv(sc.rots), dv(sc.opac)
+    quat, shape, rgbw, c0 = dv(w.quat), dv(w.shape), dv(w.rgbw), dv(w.c0)
+    cam = P.Camera(sc.cam["R"], sc.cam["t"], sc.cam["fx"], sc.cam["fy"], sc.cam["cx"], sc.cam["cy"],
+                   width, height)
+    cams = cam.centre("cuda")
+    gimg = dv(sc.grad_image)
+    rgb = torch.empty((1, n, 3), device="cuda")
+    ws = torch.empty(P.raster_workspace_bytes(n, cam, cap), dtype=torch.uint8, device="cuda")
+    g = P.nasg_grad_buffers(k, n, "cuda")
+    state = {}
+
+    def app_fwd():
+        P.nasg_eval_fwd(quat, shape, rgbw, c0, means=means, cams=cams, norm=args.norm, out=rgb)
+
+    def ras_fwd():
+        state["img"], _ = P.raster_fwd(means, scales, rots, opac, rgb[0], cam, cap, workspace=ws,
+                                       check_overflow=False)
+
+    def ras_bwd():
+        state["gc"], state["go"] = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gimg, cap)
+
+    def app_bwd():
+        P.nasg_eval_bwd(quat, shape, rgbw, c0, state["gc"][None], means=means, cams=cams,
+                        norm=args.norm, grads=g)
+
+    def step():
+        app_fwd()
+        ras_fwd()
+        ras_bwd()
+        app_bwd()
+
+    ms = time_launches(step, args.steps, args.warmup)
+    parts = {name: round(time_launches(f, args.steps, 1), 4)
+             for name, f in (("appearance_fwd", app_fwd), ("raster_fwd", ras_fwd),
+                             ("raster_bwd", ras_bwd), ("appearance_bwd", app_bwd))}
+    step()
+    torch.cuda.synchronize()
+    if int(ws[:4].view(torch.int32).item()) != 0:
+        raise SystemExit("a tile list overflowed; the measurement would miss primitives")
+    log(f"training view {ms:.3f} ms/step, parts {parts}")
+    # parity: a window of the image and the colour / opacity gradients of its
+    # primitives against the oracle (upstream gradient restricted to the window
+    # in a separate, untimed backward), and the appearance stage on sampled
+    # primitives against the oracle with the device's colour gradients as input
+    x0, y0, ww, hh = 900, 500, 32, 24
+    gwin = torch.zeros_like(gimg)
+    gwin[y0:y0 + hh, x0:x0 + ww] = gimg[y0:y0 + hh, x0:x0 + ww]
+    gcw, gow = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gwin, cap)
+    rgb_np = rgb[0].cpu().numpy()
+    p = RR.project(sc.means, sc.scales, sc.rots, sc.cam)
+    ex = 3 * np.sqrt(p["cov2"][:, 0, 0]) + 1
+    ey = 3 * np.sqrt(p["cov2"][:, 1, 1]) + 1
+    keep = p["vis"] & (p["u"] + ex >= x0) & (p["u"] - ex <= x0 + ww) & \
+        (p["v"] + ey >= y0) & (p["v"] - ey <= y0 + hh)
+    idx = np.nonzero(keep)[0]
+    wcam = dict(sc.cam, cx=sc.cam["cx"] - x0, cy=sc.cam["cy"] - y0, width=ww, height=hh)
+    ref, scale = RR.render(sc.means[idx], sc.scales[idx], sc.rots[idx], sc.opac[idx], rgb_np[idx],
+                           wcam, grad_image=sc.grad_image[y0:y0 + hh, x0:x0 + ww])
+    img = state["img"].cpu().numpy()
+    par = {"image_window": float(M.scaled_error(img[y0:y0 + hh, x0:x0 + ww], ref["image"],
+                                                scale["image"]).max()),
+           "grad_colors_window": float(M.scaled_error(gcw.cpu().numpy()[idx], ref["colors"],
+                                                      scale["colors"]).max()),
+           "grad_opac_window": float(M.scaled_error(gow.cpu().numpy()[idx], ref["opac"],
+                                                    scale["opac"]).max()),
+           "window_primitives": int(len(idx))}
+    sidx = np.sort(np.random.default_rng(0).choice(n, size=256, replace=False))
+    sub = W.take_primitives(w, sidx)
+    gc_np = state["gc"].cpu().numpy()[sidx][None]
+    o = cams.cpu().numpy()
+    code = R.NORM_EXACT if args.norm == "exact" else R.NORM_APPROX
+    aref, ascale = R.forward_backward(sub.quat, sub.shape, sub.rgbw, sub.c0, gc_np, code,
+                                      means=sc.means[sidx], cams=o)
+    got = {"rgb": rgb[:, sidx].cpu().numpy(), "quat": g["quat"][:, sidx].cpu().numpy(),
+           "shape": g["shape"][:, sidx].cpu().numpy(), "rgbw": g["rgbw"][:, :, sidx].cpu().numpy(),
+           "c0": g["c0"][sidx].cpu().numpy(), "means": g["geom"][sidx].cpu().numpy()}
+    for key_, v_ in got.items():
+        par[f"appearance_{key_}"] = float(M.scaled_error(v_, aref[key_], ascale[key_]).max())
+    log(f"parity {par}")
+    tiles = ((width + 15) // 16) * ((height + 15) // 16)
+    return dict(value=round(n / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32 (f64 compositing sums)",
+                config={"workload": f"one training view: NASGabor K={k} colours of {n} primitives for "
+                                    f"one camera, composited into {width}x{height}, compositing and "
+                                    f"appearance backward ({args.norm} normaliser)",
+                        "primitives": n, "lobes": k, "views": 1, "width": width, "height": height,
+                        "tile_capacity": cap, "tiles": tiles},
+                roofline=None, parts_ms=parts, parity_max_scaled_error=par)
 
 
 def main():
@@ -416,11 +525,13 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params",
-                             "families"],
+                             "families", "training-view"],
                     help="headline: K=8, 3 M primitives x 16 cameras; single-camera: K=8, 1 M x 1; "
                          "bf16-k16: K=16, 6 M x 8, bf16 storage; uneven-batch: 32 scenes in one "
                          "persistent launch; paper-params: the headline sizes with the paper's raw "
-                         "lobe values; families: every lobe family at the headline sizes")
+                         "lobe values; families: every lobe family at the headline sizes; "
+                         "training-view: K=8 colours of 3 M primitives for one camera composited "
+                         "into 1920x1080, with both backwards")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the path shards by primitive with no "

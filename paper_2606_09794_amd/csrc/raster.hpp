@@ -15,8 +15,9 @@ struct ProjRec {
   double u, v;        // pixel-space mean
   double a, b, c;     // inverse projected covariance: q = a dx^2 + 2 b dx dy + c dy^2
   double z;           // camera depth of the mean (sort key)
-  int32_t tx0, tx1;   // inclusive tile range touched (empty when tx0 > tx1)
-  int32_t ty0, ty1;
+  float ex, ey;       // half-extents of the q <= 9 ellipse, rounded outward
+  int16_t tx0, tx1;   // inclusive tile range touched (empty when tx0 > tx1)
+  int16_t ty0, ty1;
 };
 static_assert(sizeof(ProjRec) == 64, "projection record is one 64-byte line");
 

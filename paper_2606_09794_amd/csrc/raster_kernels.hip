@@ -19,8 +19,10 @@
 //             beyond it are dropped and flagged);
 //   sort    : per tile, the list is sorted by (depth, primitive index) in
 //             LDS (bitonic), which fixes the compositing order;
-//   render  : one 256-thread block per tile (one pixel per thread), front to
-//             back over the list in chunks staged through LDS. The support
+//   render  : one block per tile, each lane one or more pixels of one column
+//             (they share the entry's dx terms), front to back over the list
+//             in chunks staged through LDS; an entry's q <= 9 box decides per
+//             row band whether a wavefront looks at it at all. The support
 //             test and the quadratic form are FP64 (so both sides of a
 //             parity check take the same support decisions), rho = exp(-q/2)
 //             is FP32, and the transmittance (with an explicit power-of-two
@@ -30,14 +32,15 @@
 //             and dC/dalpha_i = T_i (c_i - R_{i+1}), R the colour seen from
 //             the next layer on in units of its transmittance, built by a
 //             convex-combination recursion (no cancellation at any depth),
-//             and T_i recovered from the forward's final transmittance. A
-//             wavefront (4 x 16 pixels) sums its pixels' terms for a
-//             primitive in registers and adds them to FP64 per-primitive
-//             accumulators with one atomic per value; a last kernel rounds
-//             the accumulators to the float32 outputs.
+//             and T_i recovered from the forward's final transmittance. Per
+//             primitive, a lane sums its pixels' terms, the wavefront
+//             sums over lanes in registers, and one lane adds the sums to
+//             FP64 per-primitive accumulators with one atomic per value; a
+//             last kernel rounds the accumulators to the float32 outputs.
 #include <hip/hip_runtime.h>
 
 #include "../../include/nasg.h"
+#include "nasg_device.hpp"
 #include "raster.hpp"
 
 namespace nasg {
@@ -45,7 +48,6 @@ namespace nasg {
 constexpr double kNear = 0.2;
 constexpr float kClamp = 0.99f;
 constexpr double kSupport = 9.0;
-constexpr int kChunk = 256;
 
 __global__ void raster_zero(int32_t* cursor, int64_t n_tiles, int32_t* overflow) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -126,16 +128,20 @@ __global__ void raster_project(RasterArgs a) {
       rec.a = syy * id;
       rec.b = -sxy * id;
       rec.c = sxx * id;
-      // q <= 9 implies |dx| <= 3 sqrt(sxx) and |dy| <= 3 sqrt(syy); one pixel
-      // of margin absorbs rounding; pixel px has its centre at px + 1/2
-      const double ex = 3.0 * sqrt(sxx) + 1.0, ey = 3.0 * sqrt(syy) + 1.0;
-      const double px0 = fmax(rec.u - ex - 0.5, 0.0), px1 = fmin(rec.u + ex - 0.5, a.width - 1.0);
-      const double py0 = fmax(rec.v - ey - 0.5, 0.0), py1 = fmin(rec.v + ey - 0.5, a.height - 1.0);
+      // q <= 9 implies |dx| <= 3 sqrt(sxx) and |dy| <= 3 sqrt(syy). The
+      // float half-extents are rounded outward (relative 1e-5 plus 1e-2
+      // pixel, far above the rounding of the inverse), and binning adds a
+      // pixel more; pixel px has its centre at px + 1/2
+      const double ex = 3.0 * sqrt(sxx), ey = 3.0 * sqrt(syy);
+      rec.ex = static_cast<float>(ex * (1.0 + 1e-5) + 1e-2);
+      rec.ey = static_cast<float>(ey * (1.0 + 1e-5) + 1e-2);
+      const double px0 = fmax(rec.u - ex - 1.5, 0.0), px1 = fmin(rec.u + ex + 0.5, a.width - 1.0);
+      const double py0 = fmax(rec.v - ey - 1.5, 0.0), py1 = fmin(rec.v + ey + 0.5, a.height - 1.0);
       if (px0 <= px1 && py0 <= py1) {
-        rec.tx0 = static_cast<int32_t>(px0) / kTile;
-        rec.tx1 = static_cast<int32_t>(px1) / kTile;
-        rec.ty0 = static_cast<int32_t>(py0) / kTile;
-        rec.ty1 = static_cast<int32_t>(py1) / kTile;
+        rec.tx0 = static_cast<int16_t>(static_cast<int32_t>(px0) / kTile);
+        rec.tx1 = static_cast<int16_t>(static_cast<int32_t>(px1) / kTile);
+        rec.ty0 = static_cast<int16_t>(static_cast<int32_t>(py0) / kTile);
+        rec.ty1 = static_cast<int16_t>(static_cast<int32_t>(py1) / kTile);
       }
     }
   }
@@ -212,19 +218,26 @@ __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
 
 struct StageEntry {
   double u, v, a, b, c;
+  float bx0, bx1, by0, by1;  // the entry's q <= 9 box in pixel coordinates (outward)
   float sigma, c0, c1, c2;
   int32_t idx;
   int32_t pad;
 };
 
+// Sum over the 64 lanes of a wavefront (every lane active): DPP row sums;
+// row_bcast:15 adds row 0's sum into row 1 and row 2's into row 3;
+// row_bcast:31 adds lane 31 (rows 0 + 1) into rows 2 and 3; lane 63 then
+// holds the total, read out as a uniform value.
 __device__ inline float wave_sum(float x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  x = group_sum<16>(x);
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Transmittance as t * 2^E (E a multiple of kRenorm, t kept away from the
 // bottom of the double range), so a pixel behind thousands of layers keeps
-// its exact value for the backward's division-based recovery.
+// its exact value for the backward's recovery by division.
 constexpr int kRenorm = 600;
 
 __device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int e,
@@ -237,6 +250,10 @@ __device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int
   s.a = r.a;
   s.b = r.b;
   s.c = r.c;
+  s.bx0 = static_cast<float>(r.u) - r.ex;
+  s.bx1 = static_cast<float>(r.u) + r.ex;
+  s.by0 = static_cast<float>(r.v) - r.ey;
+  s.by1 = static_cast<float>(r.v) + r.ey;
   s.sigma = a.opac[idx];
   s.c0 = a.colors[3 * idx];
   s.c1 = a.colors[3 * idx + 1];
@@ -246,58 +263,112 @@ __device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int
   *slot = s;
 }
 
-__device__ inline double quad_form(const StageEntry& s, double cxp, double cyp) {
-  const double dx = cxp - s.u, dy = cyp - s.v;
-  return s.a * dx * dx + 2.0 * s.b * dx * dy + s.c * dy * dy;
+// Thread layout of the render kernels: a block of 256 / RPL threads per
+// 16 x 16 tile; lane l of wavefront w owns column l & 15 and the RPL rows
+// 4 RPL w + (l >> 4) + 4 j, j < RPL, so an entry's dx terms are shared by a
+// lane's RPL pixels, and a wavefront skips a row band j (rows 4 RPL w + 4 j
+// .. + 3) whose pixel-centre rows the entry's box misses.
+// Rows per lane, measured on MI355X at 3 M primitives and 1920 x 1080: the
+// forward is fastest at one pixel per thread (occupancy hides the LDS and
+// FP64 latencies), the backward at two (the per-entry wavefront sums are
+// shared by two pixels per lane while four would cost occupancy).
+constexpr int kFwdRows = 1;
+constexpr int kBwdRows = 2;
+
+template <int RPL>
+struct TileMap {
+  int px, py0;               // the lane's column and first row
+  float tx0, tx1;            // the tile's pixel-centre column range
+  float ty0;                 // pixel-centre row of the wavefront's first band
+  bool in_x;
+  int height;
+};
+
+template <int RPL>
+__device__ inline TileMap<RPL> tile_map(const RasterArgs& a, int64_t tile) {
+  TileMap<RPL> m;
+  const int tx = static_cast<int>(tile % a.tiles_x), ty = static_cast<int>(tile / a.tiles_x);
+  const int lane = static_cast<int>(threadIdx.x) & 63, wave = static_cast<int>(threadIdx.x) >> 6;
+  const int row0 = ty * kTile + 4 * RPL * wave;
+  m.px = tx * kTile + (lane & 15);
+  m.py0 = row0 + (lane >> 4);
+  m.tx0 = tx * kTile + 0.5f;
+  m.tx1 = tx * kTile + 15.5f;
+  m.ty0 = row0 + 0.5f;
+  m.in_x = m.px < a.width;
+  m.height = a.height;
+  return m;
 }
 
-__global__ __launch_bounds__(256) void raster_render_fwd(RasterArgs a) {
-  __shared__ StageEntry stage[kChunk];
+template <int RPL>
+__device__ inline bool band_misses(const StageEntry& s, const TileMap<RPL>& m, int j) {
+  const float y0 = m.ty0 + 4.0f * j;
+  return s.by1 < y0 || s.by0 > y0 + 3.0f;
+}
+
+template <int RPL>
+__global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
+  constexpr int kBlock = 256 / RPL;
+  __shared__ StageEntry stage[kBlock];
   const int64_t tile = blockIdx.x;
-  const int tx = static_cast<int>(tile % a.tiles_x), ty = static_cast<int>(tile / a.tiles_x);
-  const int px = tx * kTile + static_cast<int>(threadIdx.x % kTile);
-  const int py = ty * kTile + static_cast<int>(threadIdx.x / kTile);
-  const bool inside = px < a.width && py < a.height;
-  const double cxp = px + 0.5, cyp = py + 0.5;
+  const TileMap<RPL> m = tile_map<RPL>(a, tile);
+  const double cxp = m.px + 0.5;
   const int cnt = min(a.cursor[tile], a.cap);
   const int32_t* list = a.lists + tile * a.cap;
 
-  double C0 = 0.0, C1 = 0.0, C2 = 0.0;
-  double t = 1.0, pw = 1.0;  // T = t * pw, pw = 2^E
-  int E = 0;
-  for (int base = 0; base < cnt; base += kChunk) {
+  double C[RPL][3], t[RPL], pw[RPL];
+  int E[RPL];
+  bool in[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    C[j][0] = C[j][1] = C[j][2] = 0.0;
+    t[j] = 1.0;  // T = t * pw, pw = 2^E
+    pw[j] = 1.0;
+    E[j] = 0;
+    in[j] = m.in_x && m.py0 + 4 * j < m.height;
+  }
+  for (int base = 0; base < cnt; base += kBlock) {
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
     if (e < cnt) stage_entry(a, list, e, &stage[threadIdx.x]);
     __syncthreads();
-    const int lim = min(kChunk, cnt - base);
-    if (!inside) continue;
+    const int lim = min(kBlock, cnt - base);
     for (int k = 0; k < lim; ++k) {
       const StageEntry& s = stage[k];
-      const double q = quad_form(s, cxp, cyp);
-      if (q <= kSupport) {
-        const float rho = __expf(static_cast<float>(-0.5 * q));
-        const float al = fminf(s.sigma * rho, kClamp);
-        const double w = static_cast<double>(al) * t * pw;
-        C0 = fma(w, static_cast<double>(s.c0), C0);
-        C1 = fma(w, static_cast<double>(s.c1), C1);
-        C2 = fma(w, static_cast<double>(s.c2), C2);
-        t *= 1.0 - static_cast<double>(al);
-        if (t < 0x1p-600) {
-          t *= 0x1p600;
-          E -= kRenorm;
-          pw = ldexp(1.0, E);
+      if (s.bx1 < m.tx0 || s.bx0 > m.tx1) continue;  // uniform
+      const double dx = cxp - s.u;
+      const double A = s.a * dx * dx, B = 2.0 * s.b * dx;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        if (band_misses(s, m, j)) continue;  // uniform
+        const double dy = (m.py0 + 4 * j + 0.5) - s.v;
+        const double q = fma(dy, fma(s.c, dy, B), A);
+        if (in[j] && q <= kSupport) {
+          const float rho = __expf(static_cast<float>(-0.5 * q));
+          const float al = fminf(s.sigma * rho, kClamp);
+          const double w = static_cast<double>(al) * t[j] * pw[j];
+          C[j][0] = fma(w, static_cast<double>(s.c0), C[j][0]);
+          C[j][1] = fma(w, static_cast<double>(s.c1), C[j][1]);
+          C[j][2] = fma(w, static_cast<double>(s.c2), C[j][2]);
+          t[j] *= 1.0 - static_cast<double>(al);
+          if (t[j] < 0x1p-600) {
+            t[j] *= 0x1p600;
+            E[j] -= kRenorm;
+            pw[j] = ldexp(1.0, E[j]);
+          }
         }
       }
     }
   }
-  if (inside) {
-    const int64_t pix = static_cast<int64_t>(py) * a.width + px;
-    a.image_out[3 * pix] = static_cast<float>(C0);
-    a.image_out[3 * pix + 1] = static_cast<float>(C1);
-    a.image_out[3 * pix + 2] = static_cast<float>(C2);
-    a.pix_state[2 * pix] = t;
-    a.pix_state[2 * pix + 1] = static_cast<double>(E);
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    if (!in[j]) continue;
+    const int64_t pix = static_cast<int64_t>(m.py0 + 4 * j) * a.width + m.px;
+    a.image_out[3 * pix] = static_cast<float>(C[j][0]);
+    a.image_out[3 * pix + 1] = static_cast<float>(C[j][1]);
+    a.image_out[3 * pix + 2] = static_cast<float>(C[j][2]);
+    a.pix_state[2 * pix] = t[j];
+    a.pix_state[2 * pix + 1] = static_cast<double>(E[j]);
   }
 }
 
@@ -307,68 +378,86 @@ __global__ __launch_bounds__(256) void raster_render_fwd(RasterArgs a) {
 // alpha_i) R_{i+1}, so dC/dalpha_i = T_i (c_i - R_{i+1}): no difference of
 // large sums, whatever the depth. T_i is recovered from the forward's final
 // transmittance, T_i = T_{i+1} / (1 - alpha_i).
-__global__ __launch_bounds__(256) void raster_render_bwd(RasterArgs a) {
-  __shared__ StageEntry stage[kChunk];
+template <int RPL>
+__global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
+  constexpr int kBlock = 256 / RPL;
+  __shared__ StageEntry stage[kBlock];
   const int64_t tile = blockIdx.x;
-  const int tx = static_cast<int>(tile % a.tiles_x), ty = static_cast<int>(tile / a.tiles_x);
-  const int px = tx * kTile + static_cast<int>(threadIdx.x % kTile);
-  const int py = ty * kTile + static_cast<int>(threadIdx.x / kTile);
-  const bool inside = px < a.width && py < a.height;
-  const double cxp = px + 0.5, cyp = py + 0.5;
+  const TileMap<RPL> m = tile_map<RPL>(a, tile);
+  const double cxp = m.px + 0.5;
   const int cnt = min(a.cursor[tile], a.cap);
   const int32_t* list = a.lists + tile * a.cap;
 
-  double t = 1.0, pw = 1.0;
-  int E = 0;
-  double R0 = 0.0, R1 = 0.0, R2 = 0.0;
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  if (inside) {
-    const int64_t pix = static_cast<int64_t>(py) * a.width + px;
-    t = a.pix_state[2 * pix];
-    E = static_cast<int>(a.pix_state[2 * pix + 1]);
-    pw = ldexp(1.0, E);
-    g0 = a.grad_image[3 * pix];
-    g1 = a.grad_image[3 * pix + 1];
-    g2 = a.grad_image[3 * pix + 2];
+  double t[RPL], pw[RPL], R[RPL][3];
+  float g[RPL][3];
+  int E[RPL];
+  bool in[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    in[j] = m.in_x && m.py0 + 4 * j < m.height;
+    R[j][0] = R[j][1] = R[j][2] = 0.0;
+    t[j] = 1.0;
+    pw[j] = 1.0;
+    E[j] = 0;
+    g[j][0] = g[j][1] = g[j][2] = 0.f;
+    if (in[j]) {
+      const int64_t pix = static_cast<int64_t>(m.py0 + 4 * j) * a.width + m.px;
+      t[j] = a.pix_state[2 * pix];
+      E[j] = static_cast<int>(a.pix_state[2 * pix + 1]);
+      pw[j] = ldexp(1.0, E[j]);
+      g[j][0] = a.grad_image[3 * pix];
+      g[j][1] = a.grad_image[3 * pix + 1];
+      g[j][2] = a.grad_image[3 * pix + 2];
+    }
   }
-  for (int end = cnt; end > 0; end -= kChunk) {
-    const int base = max(0, end - kChunk);
+  for (int end = cnt; end > 0; end -= kBlock) {
+    const int base = max(0, end - kBlock);
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
     if (e < end) stage_entry(a, list, e, &stage[threadIdx.x]);
     __syncthreads();
     for (int k = end - base - 1; k >= 0; --k) {
       const StageEntry& s = stage[k];
-      const double q = quad_form(s, cxp, cyp);
-      const bool hit = inside && q <= kSupport;
+      if (s.bx1 < m.tx0 || s.bx0 > m.tx1) continue;  // uniform
+      const double dx = cxp - s.u;
+      const double A = s.a * dx * dx, B = 2.0 * s.b * dx;
+      const double c0 = s.c0, c1 = s.c1, c2 = s.c2;
       float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gop = 0.f;
-      if (hit) {
-        const float rho = __expf(static_cast<float>(-0.5 * q));
-        const float raw = s.sigma * rho;
-        const float al = fminf(raw, kClamp);
-        const double ald = static_cast<double>(al);
-        const double om = 1.0 - ald;
-        t /= om;  // now T_i = t * pw
-        if (t > 0x1p300 && E < 0) {
-          t *= 0x1p-600;
-          E += kRenorm;
-          pw = ldexp(1.0, E);
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        if (band_misses(s, m, j)) continue;  // uniform
+        const double dy = (m.py0 + 4 * j + 0.5) - s.v;
+        const double q = fma(dy, fma(s.c, dy, B), A);
+        if (in[j] && q <= kSupport) {
+          any = true;
+          const float rho = __expf(static_cast<float>(-0.5 * q));
+          const float raw = s.sigma * rho;
+          const float al = fminf(raw, kClamp);
+          const double ald = static_cast<double>(al);
+          const double om = 1.0 - ald;
+          t[j] *= rcp64(om);  // now T_i = t * pw
+          if (t[j] > 0x1p300 && E[j] < 0) {
+            t[j] *= 0x1p-600;
+            E[j] += kRenorm;
+            pw[j] = ldexp(1.0, E[j]);
+          }
+          const double T = t[j] * pw[j];
+          const double w = ald * T;
+          gc0 += static_cast<float>(w * g[j][0]);
+          gc1 += static_cast<float>(w * g[j][1]);
+          gc2 += static_cast<float>(w * g[j][2]);
+          if (raw < kClamp) {
+            const double da = g[j][0] * (c0 - R[j][0]) + g[j][1] * (c1 - R[j][1]) +
+                              g[j][2] * (c2 - R[j][2]);
+            gop += static_cast<float>(da * T * rho);
+          }
+          R[j][0] = fma(om, R[j][0], ald * c0);
+          R[j][1] = fma(om, R[j][1], ald * c1);
+          R[j][2] = fma(om, R[j][2], ald * c2);
         }
-        const double T = t * pw;
-        const double w = ald * T;
-        gc0 = static_cast<float>(w * g0);
-        gc1 = static_cast<float>(w * g1);
-        gc2 = static_cast<float>(w * g2);
-        const double c0 = s.c0, c1 = s.c1, c2 = s.c2;
-        if (raw < kClamp) {
-          const double da = g0 * (c0 - R0) + g1 * (c1 - R1) + g2 * (c2 - R2);
-          gop = static_cast<float>(da * T * rho);
-        }
-        R0 = fma(om, R0, ald * c0);
-        R1 = fma(om, R1, ald * c1);
-        R2 = fma(om, R2, ald * c2);
       }
-      if (__ballot(hit) != 0) {  // wave-uniform: every lane reads the same staged entry
+      if (__ballot(any) != 0) {  // uniform: every lane reads the same staged entry
         gc0 = wave_sum(gc0);
         gc1 = wave_sum(gc1);
         gc2 = wave_sum(gc2);
@@ -397,13 +486,13 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
     }
     const size_t sm = static_cast<size_t>(a.cap_pow2) * (sizeof(double) + sizeof(int32_t));
     hipLaunchKernelGGL(raster_sort, dim3(static_cast<unsigned>(n_tiles)), dim3(256), sm, s, a);
-    hipLaunchKernelGGL(raster_render_fwd, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
-                       a);
+    hipLaunchKernelGGL(raster_render_fwd<kFwdRows>, dim3(static_cast<unsigned>(n_tiles)),
+                       dim3(256 / kFwdRows), 0, s, a);
   } else {
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(raster_zero_acc, dim3(gn), dim3(256), 0, s, a.grad_acc, a.n);
-    hipLaunchKernelGGL(raster_render_bwd, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
-                       a);
+    hipLaunchKernelGGL(raster_render_bwd<kBwdRows>, dim3(static_cast<unsigned>(n_tiles)),
+                       dim3(256 / kBwdRows), 0, s, a);
     hipLaunchKernelGGL(raster_finish_grads, dim3(gn), dim3(256), 0, s, a.grad_acc, a.grad_colors,
                        a.grad_opac, a.n);
   }
