@@ -206,8 +206,6 @@ int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, co
   a->tiles_x = L.tiles_x;
   a->tiles_y = L.tiles_y;
   a->cap = cap;
-  a->cap_pow2 = 1;
-  while (a->cap_pow2 < cap) a->cap_pow2 <<= 1;
   unsigned char* base = static_cast<unsigned char*>(const_cast<void*>(ws));
   a->overflow = reinterpret_cast<int32_t*>(base);
   a->cursor = reinterpret_cast<int32_t*>(base + L.cursor_off);

@@ -9,7 +9,7 @@
 namespace nasg {
 
 constexpr int kTile = 16;              // tile edge in pixels (one 256-thread block)
-constexpr int kMaxTileCapacity = 4096; // entries per tile list (sorted in 48 KiB of LDS)
+constexpr int kMaxTileCapacity = 4096; // entries per tile list (sorted in 32 KiB of LDS)
 
 struct ProjRec {
   double u, v;        // pixel-space mean
@@ -33,7 +33,7 @@ struct RasterArgs {
   double fx, fy, cx, cy;
   int32_t width, height;
   int32_t tiles_x, tiles_y;
-  int32_t cap, cap_pow2;
+  int32_t cap;
   // workspace views
   int32_t* overflow;
   int32_t* cursor;   // [tiles]

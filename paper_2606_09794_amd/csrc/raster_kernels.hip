@@ -17,8 +17,9 @@
 //   bin     : each primitive appends itself to the lists of those tiles
 //             (an atomic cursor per tile, fixed capacity per tile; entries
 //             beyond it are dropped and flagged);
-//   sort    : per tile, the list is sorted by (depth, primitive index) in
-//             LDS (bitonic), which fixes the compositing order;
+//   sort    : per tile, the list is sorted by (depth, primitive index) with
+//             a bitonic network on 64-bit keys held in registers and LDS,
+//             which fixes the compositing order;
 //   render  : one block per tile, each lane one or more pixels of one column
 //             (they share the entry's dx terms), front to back over the list
 //             in chunks staged through LDS; an entry's q <= 9 box decides per
@@ -165,55 +166,109 @@ __global__ void raster_bin(RasterArgs a) {
   }
 }
 
-// (depth, index) order; padding entries (index < 0) sort last
-__device__ inline bool entry_less(double za, int32_t ia, double zb, int32_t ib) {
-  if (ia < 0) return false;
-  if (ib < 0) return true;
-  return za < zb || (za == zb && ia < ib);
-}
-
-__global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
-  extern __shared__ unsigned char smem[];
-  const int64_t tile = blockIdx.x;
-  const int cnt = min(a.cursor[tile], a.cap);
-  int m = 1;
-  while (m < cnt) m <<= 1;  // m <= cap_pow2, the LDS arrays' length
-  double* kz = reinterpret_cast<double*>(smem);
-  int32_t* ki = reinterpret_cast<int32_t*>(kz + a.cap_pow2);
-  int32_t* list = a.lists + tile * a.cap;
-  for (int t = threadIdx.x; t < m; t += blockDim.x) {
-    if (t < cnt) {
-      const int32_t idx = list[t];
-      ki[t] = idx;
-      kz[t] = a.proj[idx].z;
-    } else {
-      ki[t] = -1;
-      kz[t] = 0.0;
+// Per-tile depth sort. Key = (float32 of the FP64 depth, primitive index):
+// rounding to float is monotone, so sorting the 64-bit keys orders the list
+// by depth except inside runs of equal float depth, which a final pass puts
+// in (FP64 depth, index) order; padding keys (all ones) sort last. Bitonic
+// network over 256 EPT keys, EPT consecutive keys per thread in registers:
+// strides below EPT are exchanged in registers, larger ones through LDS.
+template <int EPT>
+__device__ void bitonic_keys(uint64_t (&v)[EPT], uint64_t* lds) {
+  constexpr int M = 256 * EPT;
+  const int t = static_cast<int>(threadIdx.x);
+  for (int k = 2; k <= M; k <<= 1) {
+    for (int j = k >> 1; j >= EPT; j >>= 1) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        const int e = t * EPT + r, pe = e ^ j;
+        const uint64_t o = lds[pe];
+        const bool keep_min = ((e & k) == 0) == (e < pe);
+        v[r] = keep_min ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+      }
     }
-  }
-  __syncthreads();
-  for (int k = 2; k <= m; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = threadIdx.x; t < m; t += blockDim.x) {
-        const int p = t ^ jj;
-        if (p > t) {
-          const bool up = (t & k) == 0;
-          const bool sw = up ? entry_less(kz[p], ki[p], kz[t], ki[t])
-                             : entry_less(kz[t], ki[t], kz[p], ki[p]);
-          if (sw) {
-            const double z = kz[t];
-            kz[t] = kz[p];
-            kz[p] = z;
-            const int32_t x = ki[t];
-            ki[t] = ki[p];
-            ki[p] = x;
+#pragma unroll
+    for (int jj = EPT / 2; jj >= 1; jj >>= 1) {
+      if (jj < k) {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+          const int p = r ^ jj;
+          if (p > r) {
+            const bool up = ((t * EPT + r) & k) == 0;
+            const uint64_t a = v[r], b = v[p];
+            const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+            v[r] = up ? lo : hi;
+            v[p] = up ? hi : lo;
           }
         }
       }
-      __syncthreads();
     }
   }
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) list[t] = ki[t];
+}
+
+template <int EPT>
+__device__ void sort_tile(const RasterArgs& a, int32_t* list, int cnt, uint64_t* lds) {
+  const int t = static_cast<int>(threadIdx.x);
+  uint64_t v[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const int e = t * EPT + r;
+    if (e < cnt) {
+      const int32_t idx = list[e];
+      const float zf = __double2float_rn(a.proj[idx].z);  // z > 0.2: the bits are monotone
+      v[r] = (static_cast<uint64_t>(__float_as_uint(zf)) << 32) | static_cast<uint32_t>(idx);
+    } else {
+      v[r] = ~0ull;
+    }
+  }
+  bitonic_keys<EPT>(v, lds);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
+  __syncthreads();
+  // runs of equal float depth (already in index order): a stable insertion
+  // sort by FP64 depth, done by the thread that owns the run's first entry
+  for (int e = t; e < cnt; e += 256) {
+    const uint32_t hi = static_cast<uint32_t>(lds[e] >> 32);
+    const bool start = e == 0 || static_cast<uint32_t>(lds[e - 1] >> 32) != hi;
+    if (!start || e + 1 >= cnt || static_cast<uint32_t>(lds[e + 1] >> 32) != hi) continue;
+    int end = e + 1;
+    while (end < cnt && static_cast<uint32_t>(lds[end] >> 32) == hi) ++end;
+    for (int i = e + 1; i < end; ++i) {
+      const uint64_t key = lds[i];
+      const double z = a.proj[static_cast<uint32_t>(key)].z;
+      int p = i - 1;
+      while (p >= e && a.proj[static_cast<uint32_t>(lds[p])].z > z) {
+        lds[p + 1] = lds[p];
+        --p;
+      }
+      lds[p + 1] = key;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < cnt; e += 256) list[e] = static_cast<int32_t>(static_cast<uint32_t>(lds[e]));
+}
+
+__global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
+  __shared__ uint64_t lds[256 * 16];
+  const int64_t tile = blockIdx.x;
+  const int cnt = min(a.cursor[tile], a.cap);
+  if (cnt <= 1) return;
+  int32_t* list = a.lists + tile * a.cap;
+  if (cnt <= 256) {
+    sort_tile<1>(a, list, cnt, lds);
+  } else if (cnt <= 512) {
+    sort_tile<2>(a, list, cnt, lds);
+  } else if (cnt <= 1024) {
+    sort_tile<4>(a, list, cnt, lds);
+  } else if (cnt <= 2048) {
+    sort_tile<8>(a, list, cnt, lds);
+  } else {
+    sort_tile<16>(a, list, cnt, lds);
+  }
 }
 
 struct StageEntry {
@@ -484,8 +539,7 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
       hipLaunchKernelGGL(raster_project, dim3(gn), dim3(256), 0, s, a);
       hipLaunchKernelGGL(raster_bin, dim3(gn), dim3(256), 0, s, a);
     }
-    const size_t sm = static_cast<size_t>(a.cap_pow2) * (sizeof(double) + sizeof(int32_t));
-    hipLaunchKernelGGL(raster_sort, dim3(static_cast<unsigned>(n_tiles)), dim3(256), sm, s, a);
+    hipLaunchKernelGGL(raster_sort, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(raster_render_fwd<kFwdRows>, dim3(static_cast<unsigned>(n_tiles)),
                        dim3(256 / kFwdRows), 0, s, a);
   } else {

@@ -188,3 +188,31 @@ def test_training_view_chain():
     for name, t in zip(("quat", "shape", "rgbw", "c0"), lob):
         compare(t.grad.cpu().numpy(), gl[name], sl[name], f"grad {name}", TOL)
     compare(means.grad.cpu().numpy(), gl["means"], sl["means"], "grad means", TOL)
+
+
+def test_depth_ties_and_float_equal_depths():
+    """Depths that are exactly equal (ordered by index) and depths closer than
+    a float32 ulp (equal once rounded to float32, so the sort's FP64 tie pass
+    decides) must composite in the oracle's (depth, index) order. The camera
+    is turned by 1e-6 rad about its y axis, so the camera depth of a mean at
+    z = 4 varies by under 1e-6 with x; half of the x values repeat exactly."""
+    rng = np.random.default_rng(21)
+    n = 600
+    x = rng.uniform(-0.8, 0.8, n)
+    x[: n // 2] = rng.choice(x[n // 2: n // 2 + 8], n // 2)
+    z = np.where(rng.random(n) < 0.8, 4.0, 5.0)
+    means = np.stack([x, rng.uniform(-0.6, 0.6, n), z], -1).astype(np.float32)
+    th = 1e-6
+    R = np.array([[np.cos(th), 0.0, np.sin(th)], [0.0, 1.0, 0.0], [-np.sin(th), 0.0, np.cos(th)]])
+    cam = dict(R=R, t=np.zeros(3), fx=60.0, fy=60.0, cx=32.0, cy=24.0, width=64, height=48)
+    sc = W.SplatScene(means=means,
+                      scales=np.exp(rng.uniform(np.log(0.05), np.log(0.3), (n, 3))).astype(np.float32),
+                      rots=rng.standard_normal((n, 4)).astype(np.float32),
+                      opac=rng.uniform(0.1, 0.8, n).astype(np.float32),
+                      colors=rng.standard_normal((n, 3)).astype(np.float32),
+                      grad_image=rng.standard_normal((48, 64, 3)).astype(np.float32), cam=cam)
+    p = RR.project(sc.means, sc.scales, sc.rots, cam)
+    zf = p["z"].astype(np.float32)
+    assert len(np.unique(p["z"])) > 2 * len(np.unique(zf))      # many float-equal depths
+    assert len(np.unique(p["z"])) < n                             # and exact ties
+    _check(sc)
