@@ -61,19 +61,25 @@ def sh_bytes(n, v, *, fwd=True, bwd=True):
     return b
 
 
-def kernel_source_hash():
+# the sources (and launch table) each profiled kernel is built from
+APPEARANCE_SOURCES = ("capi.hip", "nasg_device.hpp", "nasg_kernels.hip", "nasg_launch.hpp",
+                      "nasg_skeleton.hpp", "../tuning_gfx950.json")
+RASTER_SOURCES = ("capi.hip", "nasg_device.hpp", "raster.hpp", "raster_kernels.hip")
+
+
+def kernel_source_hash(files=APPEARANCE_SOURCES):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_09794_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+            h.update(os.path.basename(f).encode() + fh.read())
     return h.hexdigest()[:16]
 
 
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (non-packed issue)
 
 
-def measured_counters(key):
+def measured_counters(key, files=APPEARANCE_SOURCES):
     """Per-launch counter figures (calibrated HBM bytes, VALU wave instructions)
     from the committed rocprofv3 summary, or None if missing or taken on other
     kernel sources."""
@@ -83,7 +89,7 @@ def measured_counters(key):
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(key)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(files):
         return None
     return ent
 
@@ -499,13 +505,26 @@ def _training_view(args, log):
         par[f"appearance_{key_}"] = float(M.scaled_error(v_, aref[key_], ascale[key_]).max())
     log(f"parity {par}")
     tiles = ((width + 15) // 16) * ((height + 15) // 16)
+    # dominant kernel: the compositing backward (raster_bwd = accumulator clear,
+    # raster_render_bwd, rounding to float32; the two small kernels take ~0.5 %)
+    counters = measured_counters(f"raster_render_bwd_n{n}_{width}x{height}", RASTER_SOURCES)
+    roofline = None
+    if counters is not None:
+        lane_ops = counters["valu_wave_instructions_per_launch"] * 64
+        ach = lane_ops / (parts["raster_bwd"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(ach, 2),
+                    "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                    "unit": "T VALU lane-instructions/s",
+                    "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
+                    "traffic": counters["bytes_per_launch"],
+                    "kernel": "raster_render_bwd (compositing backward)"}
     return dict(value=round(n / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32 (f64 compositing sums)",
                 config={"workload": f"one training view: NASGabor K={k} colours of {n} primitives for "
                                     f"one camera, composited into {width}x{height}, compositing and "
                                     f"appearance backward ({args.norm} normaliser)",
                         "primitives": n, "lobes": k, "views": 1, "width": width, "height": height,
                         "tile_capacity": cap, "tiles": tiles},
-                roofline=None, parts_ms=parts, parity_max_scaled_error=par)
+                roofline=roofline, parts_ms=parts, parity_max_scaled_error=par)
 
 
 def main():

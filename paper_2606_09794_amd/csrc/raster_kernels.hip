@@ -272,9 +272,10 @@ __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
 }
 
 struct StageEntry {
-  double u, v, a, b, c;
-  float bx0, bx1, by0, by1;  // the entry's q <= 9 box in pixel coordinates (outward)
-  float sigma, c0, c1, c2;
+  double u, v, a, b2, c;  // pixel-space mean and conic, b2 = 2 b
+  double c0, c1, c2;      // colour
+  float sigma;
+  uint32_t mask;          // row bands (rows 4 b .. 4 b + 3 of the tile) the q <= 9 box meets
   int32_t idx;
   int32_t pad;
 };
@@ -290,39 +291,69 @@ __device__ inline float wave_sum(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-// Transmittance as t * 2^E (E a multiple of kRenorm, t kept away from the
-// bottom of the double range), so a pixel behind thousands of layers keeps
-// its exact value for the backward's recovery by division.
-constexpr int kRenorm = 600;
+// Transmittance as t * 2^E (E a multiple of kRenorm). t is renormalised every
+// kRenormEvery entries of a wavefront's list and at the end of each chunk, so
+// at most kRenormEvery layers (each multiplying t by at least 0.01 going
+// forward, or dividing it by at least 0.01 going back) pass between checks:
+// t stays within [2^-500 1e-64, 1] in the forward and below 2^300 1e64 in the
+// backward, normal doubles, and a pixel behind thousands of layers keeps an
+// exact transmittance for the backward's recovery by division.
+constexpr int kRenorm = 500;
+constexpr int kRenormEvery = 32;
+// rho = exp(-q/2) = 2^(q * (-log2(e) / 2)); the constant is exact in float
+// (half of the float log2 e), so this is the float exponential of -q/2
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 
-__device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int e,
-                                   StageEntry* slot) {
+__device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int e, double x0,
+                                   double y0, StageEntry* slot) {
   const int32_t idx = list[e];
   const ProjRec r = a.proj[idx];
   StageEntry s;
   s.u = r.u;
   s.v = r.v;
   s.a = r.a;
-  s.b = r.b;
+  s.b2 = 2.0 * r.b;
   s.c = r.c;
-  s.bx0 = static_cast<float>(r.u) - r.ex;
-  s.bx1 = static_cast<float>(r.u) + r.ex;
-  s.by0 = static_cast<float>(r.v) - r.ey;
-  s.by1 = static_cast<float>(r.v) + r.ey;
-  s.sigma = a.opac[idx];
   s.c0 = a.colors[3 * idx];
   s.c1 = a.colors[3 * idx + 1];
   s.c2 = a.colors[3 * idx + 2];
+  s.sigma = a.opac[idx];
   s.idx = idx;
   s.pad = 0;
+  uint32_t mask = 0;
+  if (r.u + r.ex >= x0 + 0.5 && r.u - r.ex <= x0 + 15.5) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double ylo = y0 + 4 * b + 0.5, yhi = ylo + 3.0;
+      if (r.v + r.ey >= ylo && r.v - r.ey <= yhi) mask |= 1u << b;
+    }
+  }
+  s.mask = mask;
   *slot = s;
+}
+
+// Each wavefront lists, in order, the staged entries whose band mask meets
+// `bits`; returns the list length (uniform).
+__device__ inline int wave_compact(const StageEntry* stage, int lim, uint32_t bits,
+                                   int16_t* wl) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  int n = 0;
+  for (int g = 0; g < lim; g += 64) {
+    const int k = g + lane;
+    const bool want = k < lim && (stage[k].mask & bits) != 0;
+    const uint64_t bal = __ballot(want);
+    const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bal >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0));
+    if (want) wl[n + below] = static_cast<int16_t>(k);
+    n += __popcll(bal);
+  }
+  return n;
 }
 
 // Thread layout of the render kernels: a block of 256 / RPL threads per
 // 16 x 16 tile; lane l of wavefront w owns column l & 15 and the RPL rows
-// 4 RPL w + (l >> 4) + 4 j, j < RPL, so an entry's dx terms are shared by a
-// lane's RPL pixels, and a wavefront skips a row band j (rows 4 RPL w + 4 j
-// .. + 3) whose pixel-centre rows the entry's box misses.
+// 4 RPL w + (l >> 4) + 4 j, j < RPL (row band RPL w + j), so an entry's dx
+// terms are shared by a lane's RPL pixels.
 // Rows per lane, measured on MI355X at 3 M primitives and 1920 x 1080: the
 // forward is fastest at one pixel per thread (occupancy hides the LDS and
 // FP64 latencies), the backward at two (the per-entry wavefront sums are
@@ -332,9 +363,9 @@ constexpr int kBwdRows = 2;
 
 template <int RPL>
 struct TileMap {
-  int px, py0;               // the lane's column and first row
-  float tx0, tx1;            // the tile's pixel-centre column range
-  float ty0;                 // pixel-centre row of the wavefront's first band
+  int px, py0;     // the lane's column and first row
+  int wave;
+  double x0, y0;   // the tile's corner
   bool in_x;
   int height;
 };
@@ -343,33 +374,29 @@ template <int RPL>
 __device__ inline TileMap<RPL> tile_map(const RasterArgs& a, int64_t tile) {
   TileMap<RPL> m;
   const int tx = static_cast<int>(tile % a.tiles_x), ty = static_cast<int>(tile / a.tiles_x);
-  const int lane = static_cast<int>(threadIdx.x) & 63, wave = static_cast<int>(threadIdx.x) >> 6;
-  const int row0 = ty * kTile + 4 * RPL * wave;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  m.wave = static_cast<int>(threadIdx.x) >> 6;
   m.px = tx * kTile + (lane & 15);
-  m.py0 = row0 + (lane >> 4);
-  m.tx0 = tx * kTile + 0.5f;
-  m.tx1 = tx * kTile + 15.5f;
-  m.ty0 = row0 + 0.5f;
+  m.py0 = ty * kTile + 4 * RPL * m.wave + (lane >> 4);
+  m.x0 = tx * kTile;
+  m.y0 = ty * kTile;
   m.in_x = m.px < a.width;
   m.height = a.height;
   return m;
 }
 
 template <int RPL>
-__device__ inline bool band_misses(const StageEntry& s, const TileMap<RPL>& m, int j) {
-  const float y0 = m.ty0 + 4.0f * j;
-  return s.by1 < y0 || s.by0 > y0 + 3.0f;
-}
-
-template <int RPL>
 __global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
   constexpr int kBlock = 256 / RPL;
   __shared__ StageEntry stage[kBlock];
+  __shared__ int16_t wlist[kBlock / 64][kBlock];
   const int64_t tile = blockIdx.x;
   const TileMap<RPL> m = tile_map<RPL>(a, tile);
   const double cxp = m.px + 0.5;
-  const int cnt = min(a.cursor[tile], a.cap);
+  const int cnt = __builtin_amdgcn_readfirstlane(min(a.cursor[tile], a.cap));
   const int32_t* list = a.lists + tile * a.cap;
+  const uint32_t bits = ((1u << RPL) - 1u) << (RPL * m.wave);
+  int16_t* wl = wlist[m.wave];
 
   double C[RPL][3], t[RPL], pw[RPL];
   int E[RPL];
@@ -382,38 +409,46 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
     E[j] = 0;
     in[j] = m.in_x && m.py0 + 4 * j < m.height;
   }
+  auto renorm = [&]() {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      if (t[j] < 0x1p-500) {
+        t[j] *= 0x1p500;
+        E[j] -= kRenorm;
+        pw[j] = ldexp(1.0, E[j]);
+      }
+    }
+  };
   for (int base = 0; base < cnt; base += kBlock) {
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
-    if (e < cnt) stage_entry(a, list, e, &stage[threadIdx.x]);
+    if (e < cnt) stage_entry(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
     __syncthreads();
-    const int lim = min(kBlock, cnt - base);
-    for (int k = 0; k < lim; ++k) {
-      const StageEntry& s = stage[k];
-      if (s.bx1 < m.tx0 || s.bx0 > m.tx1) continue;  // uniform
+    const int nl = wave_compact(stage, min(kBlock, cnt - base), bits, wl);
+    __syncthreads();
+    for (int i = 0; i < nl; ++i) {
+      const StageEntry& s = stage[wl[i]];
       const double dx = cxp - s.u;
-      const double A = s.a * dx * dx, B = 2.0 * s.b * dx;
+      const double A = s.a * dx * dx, B = s.b2 * dx;
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
-        if (band_misses(s, m, j)) continue;  // uniform
+        if (RPL > 1 && ((s.mask >> (RPL * m.wave + j)) & 1u) == 0) continue;  // uniform
         const double dy = (m.py0 + 4 * j + 0.5) - s.v;
         const double q = fma(dy, fma(s.c, dy, B), A);
         if (in[j] && q <= kSupport) {
-          const float rho = __expf(static_cast<float>(-0.5 * q));
+          const float rho = __builtin_amdgcn_exp2f(static_cast<float>(q) * kNegHalfLog2e);
           const float al = fminf(s.sigma * rho, kClamp);
-          const double w = static_cast<double>(al) * t[j] * pw[j];
-          C[j][0] = fma(w, static_cast<double>(s.c0), C[j][0]);
-          C[j][1] = fma(w, static_cast<double>(s.c1), C[j][1]);
-          C[j][2] = fma(w, static_cast<double>(s.c2), C[j][2]);
-          t[j] *= 1.0 - static_cast<double>(al);
-          if (t[j] < 0x1p-600) {
-            t[j] *= 0x1p600;
-            E[j] -= kRenorm;
-            pw[j] = ldexp(1.0, E[j]);
-          }
+          const double ald = static_cast<double>(al);
+          const double w = ald * t[j] * pw[j];
+          C[j][0] = fma(w, s.c0, C[j][0]);
+          C[j][1] = fma(w, s.c1, C[j][1]);
+          C[j][2] = fma(w, s.c2, C[j][2]);
+          t[j] *= 1.0 - ald;
         }
       }
+      if ((i & (kRenormEvery - 1)) == kRenormEvery - 1) renorm();
     }
+    renorm();
   }
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
@@ -437,11 +472,14 @@ template <int RPL>
 __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
   constexpr int kBlock = 256 / RPL;
   __shared__ StageEntry stage[kBlock];
+  __shared__ int16_t wlist[kBlock / 64][kBlock];
   const int64_t tile = blockIdx.x;
   const TileMap<RPL> m = tile_map<RPL>(a, tile);
   const double cxp = m.px + 0.5;
-  const int cnt = min(a.cursor[tile], a.cap);
+  const int cnt = __builtin_amdgcn_readfirstlane(min(a.cursor[tile], a.cap));
   const int32_t* list = a.lists + tile * a.cap;
+  const uint32_t bits = ((1u << RPL) - 1u) << (RPL * m.wave);
+  int16_t* wl = wlist[m.wave];
 
   double t[RPL], pw[RPL], R[RPL][3];
   float g[RPL][3];
@@ -465,67 +503,71 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
       g[j][2] = a.grad_image[3 * pix + 2];
     }
   }
+  auto renorm = [&]() {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      if (t[j] > 0x1p300 && E[j] < 0) {
+        t[j] *= 0x1p-500;
+        E[j] += kRenorm;
+        pw[j] = ldexp(1.0, E[j]);
+      }
+    }
+  };
   for (int end = cnt; end > 0; end -= kBlock) {
     const int base = max(0, end - kBlock);
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
-    if (e < end) stage_entry(a, list, e, &stage[threadIdx.x]);
+    if (e < end) stage_entry(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
     __syncthreads();
-    for (int k = end - base - 1; k >= 0; --k) {
-      const StageEntry& s = stage[k];
-      if (s.bx1 < m.tx0 || s.bx0 > m.tx1) continue;  // uniform
+    const int nl = wave_compact(stage, end - base, bits, wl);
+    __syncthreads();
+    for (int i = nl - 1; i >= 0; --i) {
+      const StageEntry& s = stage[wl[i]];
       const double dx = cxp - s.u;
-      const double A = s.a * dx * dx, B = 2.0 * s.b * dx;
-      const double c0 = s.c0, c1 = s.c1, c2 = s.c2;
-      float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gop = 0.f;
-      bool any = false;
+      const double A = s.a * dx * dx, B = s.b2 * dx;
+      double gc0 = 0.0, gc1 = 0.0, gc2 = 0.0;
+      float gop = 0.f;
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
-        if (band_misses(s, m, j)) continue;  // uniform
+        if (RPL > 1 && ((s.mask >> (RPL * m.wave + j)) & 1u) == 0) continue;  // uniform
         const double dy = (m.py0 + 4 * j + 0.5) - s.v;
         const double q = fma(dy, fma(s.c, dy, B), A);
         if (in[j] && q <= kSupport) {
-          any = true;
-          const float rho = __expf(static_cast<float>(-0.5 * q));
+          const float rho = __builtin_amdgcn_exp2f(static_cast<float>(q) * kNegHalfLog2e);
           const float raw = s.sigma * rho;
           const float al = fminf(raw, kClamp);
           const double ald = static_cast<double>(al);
           const double om = 1.0 - ald;
           t[j] *= rcp64(om);  // now T_i = t * pw
-          if (t[j] > 0x1p300 && E[j] < 0) {
-            t[j] *= 0x1p-600;
-            E[j] += kRenorm;
-            pw[j] = ldexp(1.0, E[j]);
-          }
           const double T = t[j] * pw[j];
           const double w = ald * T;
-          gc0 += static_cast<float>(w * g[j][0]);
-          gc1 += static_cast<float>(w * g[j][1]);
-          gc2 += static_cast<float>(w * g[j][2]);
+          gc0 = fma(w, g[j][0], gc0);
+          gc1 = fma(w, g[j][1], gc1);
+          gc2 = fma(w, g[j][2], gc2);
           if (raw < kClamp) {
-            const double da = g[j][0] * (c0 - R[j][0]) + g[j][1] * (c1 - R[j][1]) +
-                              g[j][2] * (c2 - R[j][2]);
+            const double da = g[j][0] * (s.c0 - R[j][0]) + g[j][1] * (s.c1 - R[j][1]) +
+                              g[j][2] * (s.c2 - R[j][2]);
             gop += static_cast<float>(da * T * rho);
           }
-          R[j][0] = fma(om, R[j][0], ald * c0);
-          R[j][1] = fma(om, R[j][1], ald * c1);
-          R[j][2] = fma(om, R[j][2], ald * c2);
+          R[j][0] = fma(om, R[j][0], ald * s.c0);
+          R[j][1] = fma(om, R[j][1], ald * s.c1);
+          R[j][2] = fma(om, R[j][2], ald * s.c2);
         }
       }
-      if (__ballot(any) != 0) {  // uniform: every lane reads the same staged entry
-        gc0 = wave_sum(gc0);
-        gc1 = wave_sum(gc1);
-        gc2 = wave_sum(gc2);
-        gop = wave_sum(gop);
-        if ((threadIdx.x & 63) == 0) {
-          double* acc = a.grad_acc + 4 * static_cast<int64_t>(s.idx);
-          unsafeAtomicAdd(acc + 0, static_cast<double>(gc0));
-          unsafeAtomicAdd(acc + 1, static_cast<double>(gc1));
-          unsafeAtomicAdd(acc + 2, static_cast<double>(gc2));
-          unsafeAtomicAdd(acc + 3, static_cast<double>(gop));
-        }
+      const float s0 = wave_sum(static_cast<float>(gc0));
+      const float s1 = wave_sum(static_cast<float>(gc1));
+      const float s2 = wave_sum(static_cast<float>(gc2));
+      const float s3 = wave_sum(gop);
+      if ((threadIdx.x & 63) == 0 && (s0 != 0.f || s1 != 0.f || s2 != 0.f || s3 != 0.f)) {
+        double* acc = a.grad_acc + 4 * static_cast<int64_t>(s.idx);
+        unsafeAtomicAdd(acc + 0, static_cast<double>(s0));
+        unsafeAtomicAdd(acc + 1, static_cast<double>(s1));
+        unsafeAtomicAdd(acc + 2, static_cast<double>(s2));
+        unsafeAtomicAdd(acc + 3, static_cast<double>(s3));
       }
+      if ((i & (kRenormEvery - 1)) == 0) renorm();
     }
+    renorm();
   }
 }
 
