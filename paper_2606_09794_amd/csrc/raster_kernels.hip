@@ -356,10 +356,10 @@ __device__ inline int wave_compact(const StageEntry* stage, int lim, uint32_t bi
 // terms are shared by a lane's RPL pixels.
 // Rows per lane, measured on MI355X at 3 M primitives and 1920 x 1080: the
 // forward is fastest at one pixel per thread (occupancy hides the LDS and
-// FP64 latencies), the backward at two (the per-entry wavefront sums are
-// shared by two pixels per lane while four would cost occupancy).
+// FP64 latencies), the backward at four (one wavefront per tile: the four
+// per-entry wavefront sums and atomics are shared by four pixels per lane).
 constexpr int kFwdRows = 1;
-constexpr int kBwdRows = 2;
+constexpr int kBwdRows = 4;
 
 template <int RPL>
 struct TileMap {
@@ -544,14 +544,15 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
           gc0 = fma(w, g[j][0], gc0);
           gc1 = fma(w, g[j][1], gc1);
           gc2 = fma(w, g[j][2], gc2);
+          // c - R_{i+1} serves both dC/dalpha and R_i = R_{i+1} + alpha (c - R_{i+1})
+          const double d0 = s.c0 - R[j][0], d1 = s.c1 - R[j][1], d2 = s.c2 - R[j][2];
           if (raw < kClamp) {
-            const double da = g[j][0] * (s.c0 - R[j][0]) + g[j][1] * (s.c1 - R[j][1]) +
-                              g[j][2] * (s.c2 - R[j][2]);
-            gop += static_cast<float>(da * T * rho);
+            const double da = fma(g[j][0], d0, fma(g[j][1], d1, g[j][2] * d2));
+            gop += static_cast<float>(da * (T * rho));
           }
-          R[j][0] = fma(om, R[j][0], ald * s.c0);
-          R[j][1] = fma(om, R[j][1], ald * s.c1);
-          R[j][2] = fma(om, R[j][2], ald * s.c2);
+          R[j][0] = fma(ald, d0, R[j][0]);
+          R[j][1] = fma(ald, d1, R[j][1]);
+          R[j][2] = fma(ald, d2, R[j][2]);
         }
       }
       const float s0 = wave_sum(static_cast<float>(gc0));
