@@ -315,7 +315,7 @@ typedef struct nasg_gaussians {
 /* Device bytes of the workspace for n primitives, this camera and capacity
  * (0 for invalid arguments). Layout, each part 256-byte aligned: header
  * (int32 overflow flag at offset 0), tile cursors [tiles] int32, tile lists
- * [tiles][capacity] int32, projection records [N] (64 B each), the final
+ * [tiles][capacity] of 64-bit sort keys, projection records [N] (64 B each), the final
  * transmittance per pixel [H][W][2] FP64 (mantissa, power-of-two exponent)
  * and the FP64 gradient accumulators [N][4]. The workspace must be 256-byte
  * aligned. */

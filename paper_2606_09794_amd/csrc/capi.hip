@@ -165,7 +165,7 @@ bool raster_layout(int64_t n, const nasg_camera* cam, int32_t cap, RasterLayout*
   const size_t tiles = static_cast<size_t>(L->tiles_x) * L->tiles_y;
   L->cursor_off = 256;
   L->lists_off = align_up(L->cursor_off + 4 * tiles, 256);
-  L->proj_off = align_up(L->lists_off + 4 * tiles * static_cast<size_t>(cap), 256);
+  L->proj_off = align_up(L->lists_off + 8 * tiles * static_cast<size_t>(cap), 256);
   L->image_off = align_up(L->proj_off + sizeof(nasg::ProjRec) * static_cast<size_t>(n), 256);
   L->acc_off = align_up(L->image_off + 2 * sizeof(double) * static_cast<size_t>(cam->width) *
                                            static_cast<size_t>(cam->height),
@@ -209,7 +209,7 @@ int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, co
   unsigned char* base = static_cast<unsigned char*>(const_cast<void*>(ws));
   a->overflow = reinterpret_cast<int32_t*>(base);
   a->cursor = reinterpret_cast<int32_t*>(base + L.cursor_off);
-  a->lists = reinterpret_cast<int32_t*>(base + L.lists_off);
+  a->lists = reinterpret_cast<uint64_t*>(base + L.lists_off);
   a->proj = reinterpret_cast<nasg::ProjRec*>(base + L.proj_off);
   a->pix_state = reinterpret_cast<double*>(base + L.image_off);
   a->grad_acc = reinterpret_cast<double*>(base + L.acc_off);

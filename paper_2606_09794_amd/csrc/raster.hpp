@@ -37,7 +37,7 @@ struct RasterArgs {
   // workspace views
   int32_t* overflow;
   int32_t* cursor;   // [tiles]
-  int32_t* lists;    // [tiles][cap]
+  uint64_t* lists;   // [tiles][cap] keys: float32 depth bits << 32 | primitive index
   ProjRec* proj;     // [N]
   double* pix_state; // [H][W][2] forward's final transmittance t and exponent E (T = t 2^E)
   double* grad_acc;  // [N][4] backward accumulators (dL/dc, dL/dsigma)

@@ -14,9 +14,10 @@
 // Pipeline (all on the caller's stream, nothing allocated, no host sync):
 //   project : per primitive, FP64 pixel mean, inverse 2D covariance, depth and
 //             the 16 x 16-pixel tiles its ellipse's bounding box touches;
-//   bin     : each primitive appends itself to the lists of those tiles
-//             (an atomic cursor per tile, fixed capacity per tile; entries
-//             beyond it are dropped and flagged);
+//   bin     : each primitive appends its 64-bit depth key (float depth bits,
+//             index) to the lists of those tiles (an atomic cursor per tile,
+//             fixed capacity per tile; entries beyond it are dropped and
+//             flagged);
 //   sort    : per tile, the list is sorted by (depth, primitive index) with
 //             a bitonic network on 64-bit keys held in registers and LDS,
 //             which fixes the compositing order;
@@ -149,18 +150,45 @@ __global__ void raster_project(RasterArgs a) {
   a.proj[i] = rec;
 }
 
+// Sort key of a list entry: the float32 of its FP64 depth (z > 0.2, so the
+// float's bits order like the depths) above its primitive index.
+__device__ inline uint64_t depth_key(double z, int64_t i) {
+  return (static_cast<uint64_t>(__float_as_uint(__double2float_rn(z))) << 32) |
+         static_cast<uint32_t>(i);
+}
+
+// Appends each primitive's key to the lists of the tiles its box touches. The
+// cursor atomics of up to eight tiles are issued before their results are
+// used, so their latencies overlap.
 __global__ void raster_bin(RasterArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const ProjRec r = a.proj[i];
-  for (int ty = r.ty0; ty <= r.ty1; ++ty) {
-    for (int tx = r.tx0; tx <= r.tx1; ++tx) {
-      const int64_t tile = static_cast<int64_t>(ty) * a.tiles_x + tx;
-      const int32_t pos = atomicAdd(a.cursor + tile, 1);
-      if (pos < a.cap) {
-        a.lists[tile * a.cap + pos] = static_cast<int32_t>(i);
-      } else {
-        atomicMax(a.overflow, 1);
+  const int w = r.tx1 - r.tx0 + 1, h = r.ty1 - r.ty0 + 1;
+  if (w <= 0 || h <= 0) return;
+  const int area = w * h;
+  const uint64_t key = depth_key(r.z, i);
+  for (int k0 = 0; k0 < area; k0 += 8) {
+    int64_t tl[8];
+    int32_t pos[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u;
+      tl[u] = 0;
+      pos[u] = 0;
+      if (k < area) {
+        tl[u] = static_cast<int64_t>(r.ty0 + k / w) * a.tiles_x + (r.tx0 + k % w);
+        pos[u] = atomicAdd(a.cursor + tl[u], 1);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u < area) {
+        if (pos[u] < a.cap) {
+          a.lists[tl[u] * a.cap + pos[u]] = key;
+        } else {
+          atomicMax(a.overflow, 1);
+        }
       }
     }
   }
@@ -171,21 +199,25 @@ __global__ void raster_bin(RasterArgs a) {
 // by depth except inside runs of equal float depth, which a final pass puts
 // in (FP64 depth, index) order; padding keys (all ones) sort last. Bitonic
 // network over 256 EPT keys, EPT consecutive keys per thread in registers:
-// strides below EPT are exchanged in registers, larger ones through LDS.
+// strides below EPT are exchanged in registers, strides whose partner is in
+// the same wavefront by lane shuffles, the rest through LDS.
 template <int EPT>
 __device__ void bitonic_keys(uint64_t (&v)[EPT], uint64_t* lds) {
   constexpr int M = 256 * EPT;
   const int t = static_cast<int>(threadIdx.x);
   for (int k = 2; k <= M; k <<= 1) {
     for (int j = k >> 1; j >= EPT; j >>= 1) {
-      __syncthreads();
+      const int tj = j / EPT;  // partner thread t ^ tj holds the partner keys
+      if (tj >= 64) {          // another wavefront: through LDS
+        __syncthreads();
 #pragma unroll
-      for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
-      __syncthreads();
+        for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
+        __syncthreads();
+      }
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
         const int e = t * EPT + r, pe = e ^ j;
-        const uint64_t o = lds[pe];
+        const uint64_t o = tj >= 64 ? lds[pe] : __shfl_xor(v[r], tj, 64);
         const bool keep_min = ((e & k) == 0) == (e < pe);
         v[r] = keep_min ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
       }
@@ -210,20 +242,14 @@ __device__ void bitonic_keys(uint64_t (&v)[EPT], uint64_t* lds) {
 }
 
 template <int EPT>
-__device__ void sort_tile(const RasterArgs& a, int32_t* list, int cnt, uint64_t* lds) {
+__device__ void sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t* lds) {
   const int t = static_cast<int>(threadIdx.x);
+  // coalesced load through LDS into the blocked register layout
+  for (int e = t; e < 256 * EPT; e += 256) lds[e] = e < cnt ? list[e] : ~0ull;
+  __syncthreads();
   uint64_t v[EPT];
 #pragma unroll
-  for (int r = 0; r < EPT; ++r) {
-    const int e = t * EPT + r;
-    if (e < cnt) {
-      const int32_t idx = list[e];
-      const float zf = __double2float_rn(a.proj[idx].z);  // z > 0.2: the bits are monotone
-      v[r] = (static_cast<uint64_t>(__float_as_uint(zf)) << 32) | static_cast<uint32_t>(idx);
-    } else {
-      v[r] = ~0ull;
-    }
-  }
+  for (int r = 0; r < EPT; ++r) v[r] = lds[t * EPT + r];
   bitonic_keys<EPT>(v, lds);
   __syncthreads();
 #pragma unroll
@@ -249,7 +275,7 @@ __device__ void sort_tile(const RasterArgs& a, int32_t* list, int cnt, uint64_t*
     }
   }
   __syncthreads();
-  for (int e = t; e < cnt; e += 256) list[e] = static_cast<int32_t>(static_cast<uint32_t>(lds[e]));
+  for (int e = t; e < cnt; e += 256) list[e] = lds[e];
 }
 
 __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
@@ -257,7 +283,7 @@ __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
   const int64_t tile = blockIdx.x;
   const int cnt = min(a.cursor[tile], a.cap);
   if (cnt <= 1) return;
-  int32_t* list = a.lists + tile * a.cap;
+  uint64_t* list = a.lists + tile * a.cap;
   if (cnt <= 256) {
     sort_tile<1>(a, list, cnt, lds);
   } else if (cnt <= 512) {
@@ -304,9 +330,9 @@ constexpr int kRenormEvery = 32;
 // (half of the float log2 e), so this is the float exponential of -q/2
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 
-__device__ inline void stage_entry(const RasterArgs& a, const int32_t* list, int e, double x0,
+__device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, int e, double x0,
                                    double y0, StageEntry* slot) {
-  const int32_t idx = list[e];
+  const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(list[e]));
   const ProjRec r = a.proj[idx];
   StageEntry s;
   s.u = r.u;
@@ -394,7 +420,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
   const TileMap<RPL> m = tile_map<RPL>(a, tile);
   const double cxp = m.px + 0.5;
   const int cnt = __builtin_amdgcn_readfirstlane(min(a.cursor[tile], a.cap));
-  const int32_t* list = a.lists + tile * a.cap;
+  const uint64_t* list = a.lists + tile * a.cap;
   const uint32_t bits = ((1u << RPL) - 1u) << (RPL * m.wave);
   int16_t* wl = wlist[m.wave];
 
@@ -477,7 +503,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
   const TileMap<RPL> m = tile_map<RPL>(a, tile);
   const double cxp = m.px + 0.5;
   const int cnt = __builtin_amdgcn_readfirstlane(min(a.cursor[tile], a.cap));
-  const int32_t* list = a.lists + tile * a.cap;
+  const uint64_t* list = a.lists + tile * a.cap;
   const uint32_t bits = ((1u << RPL) - 1u) << (RPL * m.wave);
   int16_t* wl = wlist[m.wave];
 
