@@ -315,7 +315,8 @@ typedef struct nasg_gaussians {
 /* Device bytes of the workspace for n primitives, this camera and capacity
  * (0 for invalid arguments). Layout, each part 256-byte aligned: header
  * (int32 overflow flag at offset 0), tile cursors [tiles] int32, tile lists
- * [tiles][capacity] of 64-bit sort keys, projection records [N] (64 B each), the final
+ * [tiles][capacity] of 64-bit sort keys, render records [N] (64 B each), bin
+ * records [N] (16 B each), the final
  * transmittance per pixel [H][W][2] FP64 (mantissa, power-of-two exponent)
  * and the FP64 gradient accumulators [N][4]. The workspace must be 256-byte
  * aligned. */
@@ -334,8 +335,10 @@ int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
  * (1 - alpha_i) with S_i the colour composited behind i, evaluated back to
  * front as T_i (c_i - R_{i+1}), R_k = alpha_k c_k + (1 - alpha_k) R_{k+1};
  * dalpha/dsigma = rho below the clamp, 0 at it. Means, scales and rotations get no gradient here.
- * `workspace` must hold the forward's state for the same inputs and camera
- * (the backward overwrites only its accumulator part, so it may be repeated).
+ * `workspace` must hold the forward's state for the same inputs and camera:
+ * the backward reads the projected primitives, colours and opacities from it
+ * (the arrays in `g` are validated only) and overwrites only its accumulator
+ * part, so it may be repeated.
  * Per-pixel terms are summed per wavefront in registers and then into FP64
  * per-primitive accumulators with atomics, so the float32 results are
  * reproducible up to the order of those FP64 additions. */

@@ -152,7 +152,7 @@ nasg_batch_tuning batch_defaults(const nasg_batch_tuning* t) {
 // ---- compositing
 struct RasterLayout {
   int32_t tiles_x, tiles_y;
-  size_t cursor_off, lists_off, proj_off, image_off, acc_off, total;
+  size_t cursor_off, lists_off, rec_off, bins_off, image_off, acc_off, total;
 };
 
 bool raster_layout(int64_t n, const nasg_camera* cam, int32_t cap, RasterLayout* L) {
@@ -165,8 +165,9 @@ bool raster_layout(int64_t n, const nasg_camera* cam, int32_t cap, RasterLayout*
   const size_t tiles = static_cast<size_t>(L->tiles_x) * L->tiles_y;
   L->cursor_off = 256;
   L->lists_off = align_up(L->cursor_off + 4 * tiles, 256);
-  L->proj_off = align_up(L->lists_off + 8 * tiles * static_cast<size_t>(cap), 256);
-  L->image_off = align_up(L->proj_off + sizeof(nasg::ProjRec) * static_cast<size_t>(n), 256);
+  L->rec_off = align_up(L->lists_off + 8 * tiles * static_cast<size_t>(cap), 256);
+  L->bins_off = align_up(L->rec_off + sizeof(nasg::RenderRec) * static_cast<size_t>(n), 256);
+  L->image_off = align_up(L->bins_off + sizeof(nasg::BinRec) * static_cast<size_t>(n), 256);
   L->acc_off = align_up(L->image_off + 2 * sizeof(double) * static_cast<size_t>(cam->width) *
                                            static_cast<size_t>(cam->height),
                         256);
@@ -210,7 +211,8 @@ int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, co
   a->overflow = reinterpret_cast<int32_t*>(base);
   a->cursor = reinterpret_cast<int32_t*>(base + L.cursor_off);
   a->lists = reinterpret_cast<uint64_t*>(base + L.lists_off);
-  a->proj = reinterpret_cast<nasg::ProjRec*>(base + L.proj_off);
+  a->rec = reinterpret_cast<nasg::RenderRec*>(base + L.rec_off);
+  a->bins = reinterpret_cast<nasg::BinRec*>(base + L.bins_off);
   a->pix_state = reinterpret_cast<double*>(base + L.image_off);
   a->grad_acc = reinterpret_cast<double*>(base + L.acc_off);
   return NASG_OK;

@@ -11,15 +11,25 @@ namespace nasg {
 constexpr int kTile = 16;              // tile edge in pixels (one 256-thread block)
 constexpr int kMaxTileCapacity = 4096; // entries per tile list (sorted in 32 KiB of LDS)
 
-struct ProjRec {
-  double u, v;        // pixel-space mean
-  double a, b, c;     // inverse projected covariance: q = a dx^2 + 2 b dx dy + c dy^2
-  double z;           // camera depth of the mean (sort key)
-  float ex, ey;       // half-extents of the q <= 9 ellipse, rounded outward
-  int16_t tx0, tx1;   // inclusive tile range touched (empty when tx0 > tx1)
-  int16_t ty0, ty1;
+// What the render kernels read of a primitive, in one 64-byte record (so a
+// tile's staging gathers one line per entry): pixel-space mean, conic with
+// q = a dx^2 + b2 dx dy + c dy^2 (b2 = twice the off-diagonal), colour,
+// opacity and the q <= 9 ellipse's half-extents rounded outward.
+struct RenderRec {
+  double u, v;
+  double a, b2, c;
+  float c0, c1, c2, sigma;
+  float ex, ey;
 };
-static_assert(sizeof(ProjRec) == 64, "projection record is one 64-byte line");
+static_assert(sizeof(RenderRec) == 64, "render record is one 64-byte line");
+
+// What binning and sorting read: the camera depth of the mean (sort key) and
+// the inclusive tile range touched (empty when tx0 > tx1).
+struct BinRec {
+  double z;
+  int16_t tx0, tx1, ty0, ty1;
+};
+static_assert(sizeof(BinRec) == 16, "bin record is 16 bytes");
 
 struct RasterArgs {
   const float* means;   // [N][3]
@@ -38,7 +48,8 @@ struct RasterArgs {
   int32_t* overflow;
   int32_t* cursor;   // [tiles]
   uint64_t* lists;   // [tiles][cap] keys: float32 depth bits << 32 | primitive index
-  ProjRec* proj;     // [N]
+  RenderRec* rec;    // [N]
+  BinRec* bins;      // [N]
   double* pix_state; // [H][W][2] forward's final transmittance t and exponent E (T = t 2^E)
   double* grad_acc;  // [N][4] backward accumulators (dL/dc, dL/dsigma)
   // forward output / backward inputs and outputs

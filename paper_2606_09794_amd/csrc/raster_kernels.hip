@@ -13,7 +13,8 @@
 //
 // Pipeline (all on the caller's stream, nothing allocated, no host sync):
 //   project : per primitive, FP64 pixel mean, inverse 2D covariance, depth and
-//             the 16 x 16-pixel tiles its ellipse's bounding box touches;
+//             the 16 x 16-pixel tiles its ellipse's bounding box touches, kept
+//             with the colour and opacity in a 64-byte render record;
 //   bin     : each primitive appends its 64-bit depth key (float depth bits,
 //             index) to the lists of those tiles (an atomic cursor per tile,
 //             fixed capacity per tile; entries beyond it are dropped and
@@ -82,17 +83,18 @@ __global__ void raster_finish_grads(const double* acc, float* gc, float* go, int
 __global__ void raster_project(RasterArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  ProjRec rec{};
-  rec.tx0 = 1;  // empty tile range unless the ellipse lands on the image
-  rec.tx1 = 0;
-  rec.ty0 = 1;
-  rec.ty1 = 0;
+  RenderRec rec{};
+  BinRec bin{};
+  bin.tx0 = 1;  // empty tile range unless the ellipse lands on the image
+  bin.tx1 = 0;
+  bin.ty0 = 1;
+  bin.ty1 = 0;
   const double mx = a.means[3 * i], my = a.means[3 * i + 1], mz = a.means[3 * i + 2];
   const double* R = a.cam_rot;
   const double X = R[0] * mx + R[1] * my + R[2] * mz + a.cam_t[0];
   const double Y = R[3] * mx + R[4] * my + R[5] * mz + a.cam_t[1];
   const double Z = R[6] * mx + R[7] * my + R[8] * mz + a.cam_t[2];
-  rec.z = Z;
+  bin.z = Z;
   if (Z > kNear) {
     const double iz = 1.0 / Z;
     rec.u = a.fx * X * iz + a.cx;
@@ -128,7 +130,7 @@ __global__ void raster_project(RasterArgs a) {
     if (det > 0.0) {
       const double id = 1.0 / det;
       rec.a = syy * id;
-      rec.b = -sxy * id;
+      rec.b2 = -2.0 * sxy * id;
       rec.c = sxx * id;
       // q <= 9 implies |dx| <= 3 sqrt(sxx) and |dy| <= 3 sqrt(syy). The
       // float half-extents are rounded outward (relative 1e-5 plus 1e-2
@@ -140,14 +142,19 @@ __global__ void raster_project(RasterArgs a) {
       const double px0 = fmax(rec.u - ex - 1.5, 0.0), px1 = fmin(rec.u + ex + 0.5, a.width - 1.0);
       const double py0 = fmax(rec.v - ey - 1.5, 0.0), py1 = fmin(rec.v + ey + 0.5, a.height - 1.0);
       if (px0 <= px1 && py0 <= py1) {
-        rec.tx0 = static_cast<int16_t>(static_cast<int32_t>(px0) / kTile);
-        rec.tx1 = static_cast<int16_t>(static_cast<int32_t>(px1) / kTile);
-        rec.ty0 = static_cast<int16_t>(static_cast<int32_t>(py0) / kTile);
-        rec.ty1 = static_cast<int16_t>(static_cast<int32_t>(py1) / kTile);
+        bin.tx0 = static_cast<int16_t>(static_cast<int32_t>(px0) / kTile);
+        bin.tx1 = static_cast<int16_t>(static_cast<int32_t>(px1) / kTile);
+        bin.ty0 = static_cast<int16_t>(static_cast<int32_t>(py0) / kTile);
+        bin.ty1 = static_cast<int16_t>(static_cast<int32_t>(py1) / kTile);
       }
     }
   }
-  a.proj[i] = rec;
+  rec.c0 = a.colors[3 * i];
+  rec.c1 = a.colors[3 * i + 1];
+  rec.c2 = a.colors[3 * i + 2];
+  rec.sigma = a.opac[i];
+  a.rec[i] = rec;
+  a.bins[i] = bin;
 }
 
 // Sort key of a list entry: the float32 of its FP64 depth (z > 0.2, so the
@@ -163,7 +170,7 @@ __device__ inline uint64_t depth_key(double z, int64_t i) {
 __global__ void raster_bin(RasterArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const ProjRec r = a.proj[i];
+  const BinRec r = a.bins[i];
   const int w = r.tx1 - r.tx0 + 1, h = r.ty1 - r.ty0 + 1;
   if (w <= 0 || h <= 0) return;
   const int area = w * h;
@@ -265,9 +272,9 @@ __device__ void sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t
     while (end < cnt && static_cast<uint32_t>(lds[end] >> 32) == hi) ++end;
     for (int i = e + 1; i < end; ++i) {
       const uint64_t key = lds[i];
-      const double z = a.proj[static_cast<uint32_t>(key)].z;
+      const double z = a.bins[static_cast<uint32_t>(key)].z;
       int p = i - 1;
-      while (p >= e && a.proj[static_cast<uint32_t>(lds[p])].z > z) {
+      while (p >= e && a.bins[static_cast<uint32_t>(lds[p])].z > z) {
         lds[p + 1] = lds[p];
         --p;
       }
@@ -333,17 +340,17 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, int e, double x0,
                                    double y0, StageEntry* slot) {
   const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(list[e]));
-  const ProjRec r = a.proj[idx];
+  const RenderRec r = a.rec[idx];
   StageEntry s;
   s.u = r.u;
   s.v = r.v;
   s.a = r.a;
-  s.b2 = 2.0 * r.b;
+  s.b2 = r.b2;
   s.c = r.c;
-  s.c0 = a.colors[3 * idx];
-  s.c1 = a.colors[3 * idx + 1];
-  s.c2 = a.colors[3 * idx + 2];
-  s.sigma = a.opac[idx];
+  s.c0 = r.c0;
+  s.c1 = r.c1;
+  s.c2 = r.c2;
+  s.sigma = r.sigma;
   s.idx = idx;
   s.pad = 0;
   uint32_t mask = 0;

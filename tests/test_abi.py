@@ -161,9 +161,10 @@ def test_raster_rejects(lib):
     cam = L.NasgCamera((C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1), (C.c_double * 3)(0, 0, 0),
                        100.0, 100.0, 32.0, 24.0, 64, 48)
     need = lib.nasg_raster_workspace_bytes(10, C.byref(cam), 256)
-    # 4 x 3 tiles: header, cursors, lists [12][256] of 8-byte keys, 64-byte
-    # records, per-pixel FP64 (t, E), FP64 accumulators, each part 256-byte aligned
-    assert need == 256 + 256 + 12 * 256 * 8 + 768 + 64 * 48 * 2 * 8 + 10 * 32
+    # 4 x 3 tiles: header, cursors, lists [12][256] of 8-byte keys, 64-byte render
+    # and 16-byte bin records, per-pixel FP64 (t, E), FP64 accumulators, each part
+    # 256-byte aligned
+    assert need == 256 + 256 + 12 * 256 * 8 + 768 + 256 + 64 * 48 * 2 * 8 + 10 * 32
     assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 0) == 0
     assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 4097) == 0
     assert lib.nasg_raster_workspace_bytes(-1, C.byref(cam), 256) == 0
