@@ -216,3 +216,64 @@ def test_depth_ties_and_float_equal_depths():
     assert len(np.unique(p["z"])) > 2 * len(np.unique(zf))      # many float-equal depths
     assert len(np.unique(p["z"])) < n                             # and exact ties
     _check(sc)
+
+
+def test_graph_replays_match_eager():
+    """Both compositing calls allocate, copy and synchronise nothing: captured
+    into a graph (with their output buffers), replays with eager work and
+    poisoned outputs in between reproduce the eager results (the image
+    exactly; the gradients up to the order of their FP64 atomic sums)."""
+    sc = W.draw_splat_scene(31, 400, 80, 56, scale=(0.05, 0.5))
+    d = _dev(sc)
+    cam = _camera(sc.cam)
+    gi = torch.from_numpy(sc.grad_image).cuda()
+    cap = 512
+    ws = torch.empty(P.raster_workspace_bytes(sc.n, cam, cap), dtype=torch.uint8, device="cuda")
+
+    def run():
+        img, _ = P.raster_fwd(*d, cam, cap, workspace=ws, check_overflow=False)
+        gc, go = P.raster_bwd(*d, cam, ws, gi, cap)
+        return img, gc, go
+
+    eager = [x.clone() for x in run()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(outs[0], eager[0]), rep
+        for o, e in zip(outs[1:], eager[1:]):
+            assert torch.allclose(o, e, rtol=1e-6, atol=1e-9), rep
+
+
+def test_widest_image_on_windows():
+    """The widest image the boundary accepts (32 768 pixels, 2 048 tiles in a
+    row) with 60 000 primitives: windows at the left edge, the middle and the
+    right edge against the oracle."""
+    width, height = 32768, 24
+    sc = W.draw_splat_scene(32, 60_000, width, height, scale=(1e-4, 1e-3))
+    img, gc, go = _gpu(sc, cap=1024)
+    for x0 in (0, width // 2 - 20, width - 40):
+        w, h = 40, height
+        g = np.zeros_like(sc.grad_image)
+        g[:, x0:x0 + w] = sc.grad_image[:, x0:x0 + w]
+        img_w, gc_w, go_w = _gpu(sc, cap=1024, grad_image=g)
+        idx, ref, scale = _window_oracle(sc, x0, 0, w, h)
+        assert len(idx) > 20
+        compare(img[:, x0:x0 + w], ref["image"], scale["image"], f"image window x0={x0}", TOL)
+        compare(gc_w[idx], ref["colors"], scale["colors"], f"grad colors x0={x0}", TOL)
+        compare(go_w[idx], ref["opac"], scale["opac"], f"grad opac x0={x0}", TOL)
