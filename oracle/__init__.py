@@ -14,5 +14,10 @@ nasg_ref  NASGabor value, both normalisers, analytic gradients (paper
           Section 5.1, Supplementary Materials E and F) and the quaternion /
           view-direction chain rules.
 sh3_ref   Real degree-3 spherical harmonics, value and gradient (Section 3.2).
+nasg_paper  The paper's own lobe parametrisation (Supplementary C).
+families  The other lobe families of the distribution table (Supplementary A).
+raster_ref  Compositing into an image (Section 3.1) with colour, opacity and
+          geometry gradients.
+lr_ref    Training-rate scales and schedule.
 metrics   Error metric used by the parity tests (scale-normalised error).
 """

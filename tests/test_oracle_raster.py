@@ -134,3 +134,40 @@ def test_window_render_matches_crop():
     rest = np.ones(600, bool)
     rest[idx] = False
     assert np.all(masked["colors"][rest] == 0) and np.all(masked["opac"][rest] == 0)
+
+
+def test_rotation_jacobian_against_differences():
+    rng = np.random.default_rng(8)
+    q = rng.standard_normal((5, 4))
+    jac = RR.quat_rotation_jacobian(q)
+    h = 1e-6
+    for k in range(4):
+        qp, qm = q.copy(), q.copy()
+        qp[:, k] += h
+        qm[:, k] -= h
+        num = (RR.quat_rotation(qp) - RR.quat_rotation(qm)) / (2 * h)
+        np.testing.assert_allclose(jac[..., k], num, rtol=1e-7, atol=1e-9)
+
+
+def test_geometry_gradients_against_finite_differences():
+    """dL/dmeans, dL/dscales, dL/dquaternions (through rho, with the support,
+    near plane and clamp held fixed) against central differences of the
+    rendered loss."""
+    means, scales, rots, opac, colors = _scene(13, 10)
+    cam = dict(CAM, width=24, height=20, cx=12.0, cy=10.0, fx=30.0, fy=34.0,
+               R=RR.quat_rotation(np.array([[0.97, 0.1, -0.15, 0.12]]))[0], t=np.array([0.1, -0.2, 0.3]))
+    g = np.random.default_rng(14).standard_normal((20, 24, 3))
+    out, scale = RR.render(means, scales, rots, opac, colors, cam, grad_image=g, geometry=True)
+
+    def loss(m=means, s=scales, r=rots):
+        return float((RR.render(m, s, r, opac, colors, cam)[0]["image"] * g).sum())
+    h = 1e-6
+    for name, arr, kw in (("means", means, "m"), ("scales", scales, "s"), ("rots", rots, "r")):
+        for i in range(arr.shape[0]):
+            for k in range(arr.shape[1]):
+                ap, am = arr.copy(), arr.copy()
+                ap[i, k] += h
+                am[i, k] -= h
+                num = (loss(**{kw: ap}) - loss(**{kw: am})) / (2 * h)
+                tol = 1e-6 * (np.abs(out[name][i]).max() + scale[name][i].max() + 1e-9)
+                assert abs(num - out[name][i, k]) <= tol, (name, i, k, num, out[name][i, k])
