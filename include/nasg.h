@@ -318,7 +318,7 @@ typedef struct nasg_gaussians {
  * [tiles][capacity] of 64-bit sort keys, render records [N] (64 B each), bin
  * records [N] (16 B each), the final
  * transmittance per pixel [H][W][2] FP64 (mantissa, power-of-two exponent)
- * and the FP64 gradient accumulators [N][4]. The workspace must be 256-byte
+ * and the FP64 gradient accumulators [N][10]. The workspace must be 256-byte
  * aligned. */
 size_t nasg_raster_workspace_bytes(int64_t n, const nasg_camera* cam, int32_t tile_capacity);
 
@@ -330,21 +330,29 @@ int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
                     void* workspace, size_t ws_bytes, float* image, void* stream);
 
 /* Backward of L = sum grad_image * image with respect to the colours
- * (grad_colors [N][3]) and the opacities (grad_opac [N]); either may be NULL,
- * both are overwritten. dC/dc_i = alpha_i T_i; dC/dalpha_i = T_i c_i - S_i /
- * (1 - alpha_i) with S_i the colour composited behind i, evaluated back to
- * front as T_i (c_i - R_{i+1}), R_k = alpha_k c_k + (1 - alpha_k) R_{k+1};
- * dalpha/dsigma = rho below the clamp, 0 at it. Means, scales and rotations get no gradient here.
+ * (grad_colors [N][3]), the opacities (grad_opac [N]) and, through rho, the
+ * geometry: means [N][3], scales [N][3] and quaternions [N][4] (float32, the
+ * layouts of the inputs). Every output may be NULL and is overwritten; the
+ * geometry terms are computed only when one of their outputs is given.
+ * dC/dc_i = alpha_i T_i; dC/dalpha_i = T_i c_i - S_i / (1 - alpha_i) with S_i
+ * the colour composited behind i, evaluated back to front as
+ * T_i (c_i - R_{i+1}), R_k = alpha_k c_k + (1 - alpha_k) R_{k+1};
+ * dalpha/dsigma = rho and dalpha/dq = -sigma rho / 2 below the clamp, 0 at
+ * it; q = delta^T Sigma_2^{-1} delta is differentiated through the pixel
+ * mean, Sigma_2 = M M^T, M = J R_cw R(q/|q|) S and J (FP64 chain per
+ * primitive). The support cut, the near plane and the clamp are held fixed
+ * (their jumps have no derivative). Camera parameters get no gradient.
  * `workspace` must hold the forward's state for the same inputs and camera:
  * the backward reads the projected primitives, colours and opacities from it
- * (the arrays in `g` are validated only) and overwrites only its accumulator
- * part, so it may be repeated.
+ * (of `g` only the means, scales and rots are read, by the geometry chain)
+ * and overwrites only its accumulator part, so it may be repeated.
  * Per-pixel terms are summed per wavefront in registers and then into FP64
  * per-primitive accumulators with atomics, so the float32 results are
  * reproducible up to the order of those FP64 additions. */
 int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
                     void* workspace, size_t ws_bytes, const float* grad_image,
-                    float* grad_colors, float* grad_opac, void* stream);
+                    float* grad_colors, float* grad_opac, float* grad_means,
+                    float* grad_scales, float* grad_rots, void* stream);
 
 /* Human-readable name of a status code (static storage).                    */
 const char* nasg_status_string(int status);

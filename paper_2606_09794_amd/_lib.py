@@ -87,7 +87,7 @@ EXPORTS = {
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "nasg_raster_bwd": (C.c_int, [C.POINTER(NasgGaussians), C.POINTER(NasgCamera), C.c_int32,
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_void_p]),
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "nasg_status_string": (C.c_char_p, [C.c_int]),
     "nasg_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(NasgTuning)]),

@@ -361,24 +361,27 @@ def raster_fwd(means, scales, rots, opac, colors, cam: Camera, tile_capacity: in
 
 
 def raster_bwd(means, scales, rots, opac, colors, cam: Camera, workspace, grad_image,
-               tile_capacity: int = 1024):
+               tile_capacity: int = 1024, geometry: bool = False):
     """(grad_colors [N][3], grad_opac [N]) of L = sum(grad_image * image),
-    with the workspace of the forward on the same inputs."""
+    with the workspace of the forward on the same inputs; with geometry=True
+    also (grad_means [N][3], grad_scales [N][3], grad_rots [N][4])."""
     g = _gaussians(means, scales, rots, opac, colors)
     cs = cam.struct()
     _dev(grad_image, "grad_image")
     gc = torch.empty_like(colors)
     go = torch.empty_like(opac)
+    geo = [torch.empty_like(t) for t in (means, scales, rots)] if geometry else [None] * 3
     L.check(L.lib().nasg_raster_bwd(C.byref(g), C.byref(cs), tile_capacity, _p(workspace),
                                     workspace.numel(), _p(grad_image), _p(gc), _p(go),
-                                    _stream()), "nasg_raster_bwd")
-    return gc, go
+                                    *(_p(t) for t in geo), _stream()), "nasg_raster_bwd")
+    return (gc, go, *geo) if geometry else (gc, go)
 
 
 class Rasterize(torch.autograd.Function):
     """image = Rasterize.apply(means, scales, rots, opac, colors, cam,
     tile_capacity). Gradients flow to opac and colors (the colours carry them
-    on to the appearance model); means, scales and rots get none here."""
+    on to the appearance model) and, when any of them requires it, to means,
+    scales and rots through the projection."""
 
     @staticmethod
     def forward(ctx, means, scales, rots, opac, colors, cam, tile_capacity=1024):
@@ -391,9 +394,11 @@ class Rasterize(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_image):
         means, scales, rots, opac, colors, ws = ctx.saved_tensors
-        gc, go = raster_bwd(means, scales, rots, opac, colors, ctx.cam, ws,
-                            grad_image.contiguous(), ctx.cap)
-        return None, None, None, go, gc, None, None
+        geometry = any(ctx.needs_input_grad[:3])
+        out = raster_bwd(means, scales, rots, opac, colors, ctx.cam, ws,
+                         grad_image.contiguous(), ctx.cap, geometry=geometry)
+        gm, gs, gr = out[2:] if geometry else (None, None, None)
+        return gm, gs, gr, out[1], out[0], None, None
 
 
 def render_view(quat, shape, rgbw, c0, means, scales, rots, opac, cam: Camera, *,
@@ -401,7 +406,8 @@ def render_view(quat, shape, rgbw, c0, means, scales, rots, opac, cam: Camera, *
     """One training view: the central-ray colour of every primitive for this
     camera (one appearance evaluation per primitive, Section 5.2), composited
     into the image (Section 3.1). Differentiable in the lobe parameters, c0,
-    the means (through the view direction) and the opacities."""
+    the opacities, and the means (through the view direction and the
+    projection), scales and rotations (through the projection)."""
     rgb = NasgEval.apply(quat, shape, rgbw, c0, means, cam.centre(means.device), None, norm,
                          param)
     return Rasterize.apply(means, scales, rots, opac, rgb[0], cam, tile_capacity)

@@ -171,7 +171,7 @@ bool raster_layout(int64_t n, const nasg_camera* cam, int32_t cap, RasterLayout*
   L->acc_off = align_up(L->image_off + 2 * sizeof(double) * static_cast<size_t>(cam->width) *
                                            static_cast<size_t>(cam->height),
                         256);
-  L->total = L->acc_off + 4 * sizeof(double) * static_cast<size_t>(n);
+  L->total = L->acc_off + nasg::kAccStride * sizeof(double) * static_cast<size_t>(n);
   return true;
 }
 
@@ -486,17 +486,22 @@ int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
 
 int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,
                     void* workspace, size_t ws_bytes, const float* grad_image,
-                    float* grad_colors, float* grad_opac, void* stream) {
+                    float* grad_colors, float* grad_opac, float* grad_means,
+                    float* grad_scales, float* grad_rots, void* stream) {
   nasg::RasterArgs a{};
   const int st = raster_args(g, cam, tile_capacity, workspace, ws_bytes, &a);
   if (st != NASG_OK) return st;
   if (grad_image == nullptr) return NASG_ERR_NULL;
   if (!aligned(grad_image, 4) || (grad_colors && !aligned(grad_colors, 4)) ||
-      (grad_opac && !aligned(grad_opac, 4)))
+      (grad_opac && !aligned(grad_opac, 4)) || (grad_means && !aligned(grad_means, 4)) ||
+      (grad_scales && !aligned(grad_scales, 4)) || (grad_rots && !aligned(grad_rots, 4)))
     return NASG_ERR_ALIGN;
   a.grad_image = grad_image;
   a.grad_colors = grad_colors;
   a.grad_opac = grad_opac;
+  a.grad_means = grad_means;
+  a.grad_scales = grad_scales;
+  a.grad_rots = grad_rots;
   return nasg::launch_raster(a, true, static_cast<hipStream_t>(stream)) == hipSuccess
              ? NASG_OK
              : NASG_ERR_LAUNCH;

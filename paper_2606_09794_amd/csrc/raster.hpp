@@ -10,6 +10,8 @@ namespace nasg {
 
 constexpr int kTile = 16;              // tile edge in pixels (one 256-thread block)
 constexpr int kMaxTileCapacity = 4096; // entries per tile list (sorted in 32 KiB of LDS)
+constexpr int kAccStride = 10;         // FP64 accumulators per primitive: dL/dc (3),
+                                       // dL/dsigma, dL/d(u, v, a, b, c), one spare
 
 // What the render kernels read of a primitive, in one 64-byte record (so a
 // tile's staging gathers one line per entry): pixel-space mean, conic with
@@ -51,12 +53,15 @@ struct RasterArgs {
   RenderRec* rec;    // [N]
   BinRec* bins;      // [N]
   double* pix_state; // [H][W][2] forward's final transmittance t and exponent E (T = t 2^E)
-  double* grad_acc;  // [N][4] backward accumulators (dL/dc, dL/dsigma)
+  double* grad_acc;  // [N][kAccStride] backward accumulators
   // forward output / backward inputs and outputs
   float* image_out;         // [H][W][3]
   const float* grad_image;  // [H][W][3]
   float* grad_colors;       // [N][3] or null
   float* grad_opac;         // [N] or null
+  float* grad_means;        // [N][3] or null
+  float* grad_scales;       // [N][3] or null
+  float* grad_rots;         // [N][4] or null
 };
 
 hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s);

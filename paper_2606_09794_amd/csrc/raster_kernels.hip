@@ -61,23 +61,116 @@ __global__ void raster_zero(int32_t* cursor, int64_t n_tiles, int32_t* overflow)
 __global__ void raster_zero_acc(double* acc, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) {
-    acc[4 * i + 0] = 0.0;
-    acc[4 * i + 1] = 0.0;
-    acc[4 * i + 2] = 0.0;
-    acc[4 * i + 3] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kAccStride; ++k) acc[kAccStride * i + k] = 0.0;
   }
 }
 
-__global__ void raster_finish_grads(const double* acc, float* gc, float* go, int64_t n) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    if (gc != nullptr) {
-      gc[3 * i + 0] = static_cast<float>(acc[4 * i + 0]);
-      gc[3 * i + 1] = static_cast<float>(acc[4 * i + 1]);
-      gc[3 * i + 2] = static_cast<float>(acc[4 * i + 2]);
+// Gradients of the loss with respect to a primitive's mean, scales and
+// quaternion from its sums g2 = (dL/du, dL/dv, dL/da, dL/db, dL/dc) over the
+// image (b the conic's off-diagonal entry), in FP64, by the chain through the
+// projection: K = Sigma_2^{-1} with dL/dSigma_2 = -K dL/dK K, Sigma_2 = M M^T
+// (dL/dM = 2 dL/dSigma_2 M), M = J R_cw R(q/|q|) S, and u, v and J functions
+// of the camera-space mean.
+__device__ void geometry_chain(const RasterArgs& a, int64_t i, const double* g2, float* gm,
+                               float* gs, float* gr) {
+  double out_m[3] = {0.0, 0.0, 0.0}, out_s[3] = {0.0, 0.0, 0.0}, out_q[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* R = a.cam_rot;
+  const double mx = a.means[3 * i], my = a.means[3 * i + 1], mz = a.means[3 * i + 2];
+  const double X = R[0] * mx + R[1] * my + R[2] * mz + a.cam_t[0];
+  const double Y = R[3] * mx + R[4] * my + R[5] * mz + a.cam_t[1];
+  const double Z = R[6] * mx + R[7] * my + R[8] * mz + a.cam_t[2];
+  const bool any = g2[0] != 0.0 || g2[1] != 0.0 || g2[2] != 0.0 || g2[3] != 0.0 || g2[4] != 0.0;
+  if (any && Z > kNear) {
+    const double iz = 1.0 / Z, iz2 = iz * iz;
+    double qw = a.rots[4 * i], qx = a.rots[4 * i + 1], qy = a.rots[4 * i + 2], qz = a.rots[4 * i + 3];
+    const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qn;
+    qx *= qn;
+    qy *= qn;
+    qz *= qn;
+    const double Rw[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+                             {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
+                             {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
+    const double sc[3] = {a.scales[3 * i], a.scales[3 * i + 1], a.scales[3 * i + 2]};
+    double A[3][3];  // R_cw R_w S
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        A[r][c] = (R[3 * r] * Rw[0][c] + R[3 * r + 1] * Rw[1][c] + R[3 * r + 2] * Rw[2][c]) * sc[c];
+    const double J[2][3] = {{a.fx * iz, 0.0, -a.fx * X * iz2}, {0.0, a.fy * iz, -a.fy * Y * iz2}};
+    double M[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) M[r][c] = J[r][0] * A[0][c] + J[r][1] * A[1][c] + J[r][2] * A[2][c];
+    const double sxx = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
+    const double sxy = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
+    const double syy = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
+    const double id = 1.0 / (sxx * syy - sxy * sxy);
+    const double K[2][2] = {{syy * id, -sxy * id}, {-sxy * id, sxx * id}};
+    const double gK[2][2] = {{g2[2], 0.5 * g2[3]}, {0.5 * g2[3], g2[4]}};
+    double T1[2][2], gS[2][2];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) T1[r][c] = K[r][0] * gK[0][c] + K[r][1] * gK[1][c];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) gS[r][c] = -(T1[r][0] * K[0][c] + T1[r][1] * K[1][c]);
+    double gM[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) gM[r][c] = 2.0 * (gS[r][0] * M[0][c] + gS[r][1] * M[1][c]);
+    double gJ[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) gJ[r][c] = gM[r][0] * A[c][0] + gM[r][1] * A[c][1] + gM[r][2] * A[c][2];
+    double gA[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) gA[r][c] = J[0][r] * gM[0][c] + J[1][r] * gM[1][c];
+    double gRw[3][3];
+    for (int k = 0; k < 3; ++k) {
+      for (int c = 0; c < 3; ++c) {
+        const double grs = R[k] * gA[0][c] + R[3 + k] * gA[1][c] + R[6 + k] * gA[2][c];  // (R_cw^T gA)
+        out_s[c] += grs * Rw[k][c];
+        gRw[k][c] = grs * sc[c];
+      }
     }
-    if (go != nullptr) go[i] = static_cast<float>(acc[4 * i + 3]);
+    // d R(u) / d(w, x, y, z) contracted with gRw, then the unit-norm projection
+    const double gw = 2.0 * (-gRw[0][1] * qz + gRw[0][2] * qy + gRw[1][0] * qz - gRw[1][2] * qx -
+                             gRw[2][0] * qy + gRw[2][1] * qx);
+    const double gx = 2.0 * (gRw[0][1] * qy + gRw[0][2] * qz + gRw[1][0] * qy - 2.0 * gRw[1][1] * qx -
+                             gRw[1][2] * qw + gRw[2][0] * qz + gRw[2][1] * qw - 2.0 * gRw[2][2] * qx);
+    const double gy = 2.0 * (-2.0 * gRw[0][0] * qy + gRw[0][1] * qx + gRw[0][2] * qw + gRw[1][0] * qx +
+                             gRw[1][2] * qz - gRw[2][0] * qw + gRw[2][1] * qz - 2.0 * gRw[2][2] * qy);
+    const double gz = 2.0 * (-2.0 * gRw[0][0] * qz - gRw[0][1] * qw + gRw[0][2] * qx + gRw[1][0] * qw -
+                             2.0 * gRw[1][1] * qz + gRw[1][2] * qy + gRw[2][0] * qx + gRw[2][1] * qy);
+    const double dot = gw * qw + gx * qx + gy * qy + gz * qz;
+    out_q[0] = (gw - qw * dot) * qn;
+    out_q[1] = (gx - qx * dot) * qn;
+    out_q[2] = (gy - qy * dot) * qn;
+    out_q[3] = (gz - qz * dot) * qn;
+    // camera-space mean through (u, v) and J
+    const double gX = g2[0] * a.fx * iz - gJ[0][2] * a.fx * iz2;
+    const double gY = g2[1] * a.fy * iz - gJ[1][2] * a.fy * iz2;
+    const double gZ = -g2[0] * a.fx * X * iz2 - g2[1] * a.fy * Y * iz2 - gJ[0][0] * a.fx * iz2 +
+                      gJ[0][2] * 2.0 * a.fx * X * iz2 * iz - gJ[1][1] * a.fy * iz2 +
+                      gJ[1][2] * 2.0 * a.fy * Y * iz2 * iz;
+    for (int k = 0; k < 3; ++k) out_m[k] = gX * R[k] + gY * R[3 + k] + gZ * R[6 + k];
   }
+  if (gm != nullptr)
+    for (int k = 0; k < 3; ++k) gm[3 * i + k] = static_cast<float>(out_m[k]);
+  if (gs != nullptr)
+    for (int k = 0; k < 3; ++k) gs[3 * i + k] = static_cast<float>(out_s[k]);
+  if (gr != nullptr)
+    for (int k = 0; k < 4; ++k) gr[4 * i + k] = static_cast<float>(out_q[k]);
+}
+
+template <bool GEOM>
+__global__ void raster_finish_grads(RasterArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const double* acc = a.grad_acc + kAccStride * i;
+  if (a.grad_colors != nullptr) {
+    a.grad_colors[3 * i + 0] = static_cast<float>(acc[0]);
+    a.grad_colors[3 * i + 1] = static_cast<float>(acc[1]);
+    a.grad_colors[3 * i + 2] = static_cast<float>(acc[2]);
+  }
+  if (a.grad_opac != nullptr) a.grad_opac[i] = static_cast<float>(acc[3]);
+  if constexpr (GEOM) geometry_chain(a, i, acc + 4, a.grad_means, a.grad_scales, a.grad_rots);
 }
 
 __global__ void raster_project(RasterArgs a) {
@@ -501,7 +594,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
 // alpha_i) R_{i+1}, so dC/dalpha_i = T_i (c_i - R_{i+1}): no difference of
 // large sums, whatever the depth. T_i is recovered from the forward's final
 // transmittance, T_i = T_{i+1} / (1 - alpha_i).
-template <int RPL>
+template <int RPL, bool GEOM>
 __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
   constexpr int kBlock = 256 / RPL;
   __shared__ StageEntry stage[kBlock];
@@ -560,6 +653,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
       const double A = s.a * dx * dx, B = s.b2 * dx;
       double gc0 = 0.0, gc1 = 0.0, gc2 = 0.0;
       float gop = 0.f;
+      double gu = 0.0, gv = 0.0, ga = 0.0, gb = 0.0, gcc = 0.0;  // dL/d(u, v, a, b, c)
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
         if (RPL > 1 && ((s.mask >> (RPL * m.wave + j)) & 1u) == 0) continue;  // uniform
@@ -581,7 +675,18 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
           const double d0 = s.c0 - R[j][0], d1 = s.c1 - R[j][1], d2 = s.c2 - R[j][2];
           if (raw < kClamp) {
             const double da = fma(g[j][0], d0, fma(g[j][1], d1, g[j][2] * d2));
-            gop += static_cast<float>(da * (T * rho));
+            const double gs = da * (T * rho);  // dL/dsigma of this pixel
+            gop += static_cast<float>(gs);
+            if constexpr (GEOM) {
+              // dL/dq = dL/dalpha * sigma * (-rho / 2); q = a dx^2 + 2 b dx dy + c dy^2
+              const double dq = -0.5 * static_cast<double>(s.sigma) * gs;
+              const double hb = 0.5 * s.b2;
+              gu = fma(dq, -2.0 * fma(s.a, dx, hb * dy), gu);
+              gv = fma(dq, -2.0 * fma(hb, dx, s.c * dy), gv);
+              ga = fma(dq, dx * dx, ga);
+              gb = fma(dq, 2.0 * dx * dy, gb);
+              gcc = fma(dq, dy * dy, gcc);
+            }
           }
           R[j][0] = fma(ald, d0, R[j][0]);
           R[j][1] = fma(ald, d1, R[j][1]);
@@ -593,11 +698,26 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
       const float s2 = wave_sum(static_cast<float>(gc2));
       const float s3 = wave_sum(gop);
       if ((threadIdx.x & 63) == 0 && (s0 != 0.f || s1 != 0.f || s2 != 0.f || s3 != 0.f)) {
-        double* acc = a.grad_acc + 4 * static_cast<int64_t>(s.idx);
+        double* acc = a.grad_acc + kAccStride * static_cast<int64_t>(s.idx);
         unsafeAtomicAdd(acc + 0, static_cast<double>(s0));
         unsafeAtomicAdd(acc + 1, static_cast<double>(s1));
         unsafeAtomicAdd(acc + 2, static_cast<double>(s2));
         unsafeAtomicAdd(acc + 3, static_cast<double>(s3));
+      }
+      if constexpr (GEOM) {
+        const float s4 = wave_sum(static_cast<float>(gu));
+        const float s5 = wave_sum(static_cast<float>(gv));
+        const float s6 = wave_sum(static_cast<float>(ga));
+        const float s7 = wave_sum(static_cast<float>(gb));
+        const float s8 = wave_sum(static_cast<float>(gcc));
+        if ((threadIdx.x & 63) == 0 && (s4 != 0.f || s5 != 0.f || s6 != 0.f || s7 != 0.f || s8 != 0.f)) {
+          double* acc = a.grad_acc + kAccStride * static_cast<int64_t>(s.idx) + 4;
+          unsafeAtomicAdd(acc + 0, static_cast<double>(s4));
+          unsafeAtomicAdd(acc + 1, static_cast<double>(s5));
+          unsafeAtomicAdd(acc + 2, static_cast<double>(s6));
+          unsafeAtomicAdd(acc + 3, static_cast<double>(s7));
+          unsafeAtomicAdd(acc + 4, static_cast<double>(s8));
+        }
       }
       if ((i & (kRenormEvery - 1)) == 0) renorm();
     }
@@ -620,11 +740,17 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
                        dim3(256 / kFwdRows), 0, s, a);
   } else {
     if (a.n == 0) return hipGetLastError();
+    const bool geom = a.grad_means != nullptr || a.grad_scales != nullptr || a.grad_rots != nullptr;
     hipLaunchKernelGGL(raster_zero_acc, dim3(gn), dim3(256), 0, s, a.grad_acc, a.n);
-    hipLaunchKernelGGL(raster_render_bwd<kBwdRows>, dim3(static_cast<unsigned>(n_tiles)),
-                       dim3(256 / kBwdRows), 0, s, a);
-    hipLaunchKernelGGL(raster_finish_grads, dim3(gn), dim3(256), 0, s, a.grad_acc, a.grad_colors,
-                       a.grad_opac, a.n);
+    if (geom) {
+      hipLaunchKernelGGL((raster_render_bwd<kBwdRows, true>), dim3(static_cast<unsigned>(n_tiles)),
+                         dim3(256 / kBwdRows), 0, s, a);
+      hipLaunchKernelGGL(raster_finish_grads<true>, dim3(gn), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((raster_render_bwd<kBwdRows, false>), dim3(static_cast<unsigned>(n_tiles)),
+                         dim3(256 / kBwdRows), 0, s, a);
+      hipLaunchKernelGGL(raster_finish_grads<false>, dim3(gn), dim3(256), 0, s, a);
+    }
   }
   return hipGetLastError();
 }

@@ -162,9 +162,9 @@ def test_raster_rejects(lib):
                        100.0, 100.0, 32.0, 24.0, 64, 48)
     need = lib.nasg_raster_workspace_bytes(10, C.byref(cam), 256)
     # 4 x 3 tiles: header, cursors, lists [12][256] of 8-byte keys, 64-byte render
-    # and 16-byte bin records, per-pixel FP64 (t, E), FP64 accumulators, each part
-    # 256-byte aligned
-    assert need == 256 + 256 + 12 * 256 * 8 + 768 + 256 + 64 * 48 * 2 * 8 + 10 * 32
+    # and 16-byte bin records, per-pixel FP64 (t, E), FP64 accumulators [N][10],
+    # each part 256-byte aligned
+    assert need == 256 + 256 + 12 * 256 * 8 + 768 + 256 + 64 * 48 * 2 * 8 + 10 * 80
     assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 0) == 0
     assert lib.nasg_raster_workspace_bytes(10, C.byref(cam), 4097) == 0
     assert lib.nasg_raster_workspace_bytes(-1, C.byref(cam), 256) == 0
@@ -188,9 +188,13 @@ def test_raster_rejects(lib):
     g.rots = FAKE + 1
     assert fwd() == -3
     g.rots = FAKE
-    bwd = lambda nb=need, gi=FAKE, gc=FAKE, go=FAKE: lib.nasg_raster_bwd(  # noqa: E731
-        C.byref(g), C.byref(cam), 256, FAKE, nb, gi, gc, go, None)
+    bwd = lambda nb=need, gi=FAKE, gc=FAKE, go=FAKE, gm=None, gs=None, gr=None: \
+        lib.nasg_raster_bwd(C.byref(g), C.byref(cam), 256, FAKE, nb, gi, gc, go, gm, gs, gr,  # noqa: E731
+                            None)
     assert bwd(gi=None) == -1
     assert bwd(nb=need - 8) == -7
     assert bwd(gc=FAKE + 1) == -3
     assert bwd(go=FAKE + 2) == -3
+    assert bwd(gm=FAKE + 2) == -3
+    assert bwd(gs=FAKE + 1) == -3
+    assert bwd(gr=FAKE + 3) == -3

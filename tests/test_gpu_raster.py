@@ -27,23 +27,30 @@ def _dev(sc):
     return [t(sc.means), t(sc.scales), t(sc.rots), t(sc.opac), t(sc.colors)]
 
 
-def _gpu(sc, cap=1024, grad_image=None):
+GEOM = ("means", "scales", "rots")
+
+
+def _gpu(sc, cap=1024, grad_image=None, geometry=False):
+    """image, grad colours, grad opacities (and, with geometry, grad means,
+    scales, rots) as numpy arrays."""
     d = _dev(sc)
     cam = _camera(sc.cam)
     img, ws = P.raster_fwd(*d, cam, cap)
     gi = torch.from_numpy(np.ascontiguousarray(sc.grad_image if grad_image is None else grad_image)).cuda()
-    gc, go = P.raster_bwd(*d, cam, ws, gi, cap)
+    out = P.raster_bwd(*d, cam, ws, gi, cap, geometry=geometry)
     torch.cuda.synchronize()
-    return img.cpu().numpy(), gc.cpu().numpy(), go.cpu().numpy()
+    return (img.cpu().numpy(), *(t.cpu().numpy() for t in out))
 
 
 def _check(sc, cap=1024, tol=TOL):
-    img, gc, go = _gpu(sc, cap)
+    img, gc, go, gm, gs, gr = _gpu(sc, cap, geometry=True)
     ref, scale = RR.render(sc.means, sc.scales, sc.rots, sc.opac, sc.colors, sc.cam,
-                           grad_image=sc.grad_image)
+                           grad_image=sc.grad_image, geometry=True)
     compare(img, ref["image"], scale["image"], "image", tol)
     compare(gc, ref["colors"], scale["colors"], "grad colors", tol)
     compare(go, ref["opac"], scale["opac"], "grad opac", tol)
+    for name, v in zip(GEOM, (gm, gs, gr)):
+        compare(v, ref[name], scale[name], f"grad {name}", tol)
     return img, ref
 
 
@@ -77,15 +84,15 @@ def test_opacities_at_the_clamp():
 def test_nothing_visible():
     """All primitives behind the near plane: black image, zero gradients."""
     sc = W.draw_splat_scene(4, 64, 40, 30, scale=(0.1, 0.4), behind=1.0)
-    img, gc, go = _gpu(sc)
-    assert np.all(img == 0) and np.all(gc == 0) and np.all(go == 0)
+    img, *grads = _gpu(sc, geometry=True)
+    assert np.all(img == 0) and all(np.all(v == 0) for v in grads)
 
 
 def test_empty_scene():
     sc = W.draw_splat_scene(5, 0, 33, 17)
-    img, gc, go = _gpu(sc)
+    img, gc, go, gm, gs, gr = _gpu(sc, geometry=True)
     assert img.shape == (17, 33, 3) and np.all(img == 0)
-    assert gc.shape == (0, 3) and go.shape == (0,)
+    assert gc.shape == (0, 3) and go.shape == (0,) and gr.shape == (0, 4)
 
 
 def test_tile_overflow_is_reported():
@@ -107,11 +114,14 @@ def test_backward_repeats_and_matches_autograd():
     b = P.raster_bwd(*d, cam, ws, gi)
     op = d[3].clone().requires_grad_(True)
     col = d[4].clone().requires_grad_(True)
-    out = P.Rasterize.apply(d[0], d[1], d[2], op, col, cam)
+    geo = [t.clone().requires_grad_(True) for t in d[:3]]
+    out = P.Rasterize.apply(*geo, op, col, cam)
     (out * gi).sum().backward()
+    ag = P.raster_bwd(*d, cam, ws, gi, geometry=True)
     torch.cuda.synchronize()
     assert torch.equal(out, img)
-    for x, y in ((a[0], b[0]), (a[1], b[1]), (a[0], col.grad), (a[1], op.grad)):
+    for x, y in ((a[0], b[0]), (a[1], b[1]), (a[0], col.grad), (a[1], op.grad), (ag[0], a[0]),
+                 (ag[2], geo[0].grad), (ag[3], geo[1].grad), (ag[4], geo[2].grad)):
         assert torch.allclose(x, y, rtol=1e-6, atol=1e-7)
 
 
@@ -128,7 +138,7 @@ def _window_oracle(sc, x0, y0, w, h):
     cam = dict(sc.cam, cx=sc.cam["cx"] - x0, cy=sc.cam["cy"] - y0, width=w, height=h)
     g = sc.grad_image[y0:y0 + h, x0:x0 + w]
     out, scale = RR.render(sc.means[idx], sc.scales[idx], sc.rots[idx], sc.opac[idx],
-                           sc.colors[idx], cam, grad_image=g)
+                           sc.colors[idx], cam, grad_image=g, geometry=True)
     return idx, out, scale
 
 
@@ -142,15 +152,18 @@ def test_full_size_windows(win):
     sc = W.draw_splat_scene(8, 3_000_000, 1920, 1080)
     g = np.zeros_like(sc.grad_image)
     g[y0:y0 + h, x0:x0 + w] = sc.grad_image[y0:y0 + h, x0:x0 + w]
-    img, gc, go = _gpu(sc, cap=4096, grad_image=g)
+    img, gc, go, gm, gs, gr = _gpu(sc, cap=4096, grad_image=g, geometry=True)
     idx, ref, scale = _window_oracle(sc, x0, y0, w, h)
     assert len(idx) > 500
     compare(img[y0:y0 + h, x0:x0 + w], ref["image"], scale["image"], "image window", TOL)
     compare(gc[idx], ref["colors"], scale["colors"], "grad colors", TOL)
     compare(go[idx], ref["opac"], scale["opac"], "grad opac", TOL)
+    for name, v in zip(GEOM, (gm, gs, gr)):
+        compare(v[idx], ref[name], scale[name], f"grad {name}", TOL)
     rest = np.ones(sc.n, bool)
     rest[idx] = False
-    assert np.all(gc[rest] == 0) and np.all(go[rest] == 0)
+    for v in (gc, go, gm, gs, gr):
+        assert np.all(v[rest] == 0)
 
 
 def test_training_view_chain():
@@ -187,7 +200,15 @@ def test_training_view_chain():
                                means=sc.means, cams=o)
     for name, t in zip(("quat", "shape", "rgbw", "c0"), lob):
         compare(t.grad.cpu().numpy(), gl[name], sl[name], f"grad {name}", TOL)
-    compare(means.grad.cpu().numpy(), gl["means"], sl["means"], "grad means", TOL)
+    # the means move the view direction (appearance) and the projection
+    # (compositing); the colours' own rounding enters the latter through a
+    # scale taken with the appearance scale in place of the colours
+    gref, gscale = RR.render(sc.means, sc.scales, sc.rots, sc.opac, rgb[0], sc.cam,
+                             grad_image=sc.grad_image, geometry=True)
+    _, gscale2 = RR.render(sc.means, sc.scales, sc.rots, sc.opac, s_rgb[0], sc.cam,
+                           grad_image=sc.grad_image, geometry=True)
+    compare(means.grad.cpu().numpy(), gl["means"] + gref["means"],
+            sl["means"] + gscale["means"] + gscale2["means"], "grad means", TOL)
 
 
 def test_depth_ties_and_float_equal_depths():
@@ -271,9 +292,11 @@ def test_widest_image_on_windows():
         w, h = 40, height
         g = np.zeros_like(sc.grad_image)
         g[:, x0:x0 + w] = sc.grad_image[:, x0:x0 + w]
-        img_w, gc_w, go_w = _gpu(sc, cap=1024, grad_image=g)
+        img_w, gc_w, go_w, gm_w, gs_w, gr_w = _gpu(sc, cap=1024, grad_image=g, geometry=True)
         idx, ref, scale = _window_oracle(sc, x0, 0, w, h)
         assert len(idx) > 20
         compare(img[:, x0:x0 + w], ref["image"], scale["image"], f"image window x0={x0}", TOL)
         compare(gc_w[idx], ref["colors"], scale["colors"], f"grad colors x0={x0}", TOL)
         compare(go_w[idx], ref["opac"], scale["opac"], f"grad opac x0={x0}", TOL)
+        for name, v in zip(GEOM, (gm_w, gs_w, gr_w)):
+            compare(v[idx], ref[name], scale[name], f"grad {name} x0={x0}", TOL)
