@@ -409,9 +409,10 @@ def bench_other(args, log):
 
 def _training_view(args, log):
     """One training view: NASGabor colours of every primitive along its
-    central ray for one camera, compositing into a 1920 x 1080 image,
-    the compositing backward and the appearance backward on its colour
-    gradients. One step = those four calls."""
+    central ray for one camera, compositing into a 1920 x 1080 image, the
+    compositing backward (colours, opacities, means, scales, quaternions) and
+    the appearance backward on its colour gradients. One step = those four
+    calls."""
     import torch
 
     import paper_2606_09794_amd as P
@@ -444,7 +445,12 @@ def _training_view(args, log):
                                        check_overflow=False)
 
     def ras_bwd():
-        state["gc"], state["go"] = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gimg, cap)
+        (state["gc"], state["go"], state["gm"], state["gs"],
+         state["gr"]) = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gimg, cap,
+                                     geometry=True)
+
+    def ras_bwd_colour_only():
+        P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gimg, cap)
 
     def app_bwd():
         P.nasg_eval_bwd(quat, shape, rgbw, c0, state["gc"][None], means=means, cams=cams,
@@ -459,7 +465,8 @@ def _training_view(args, log):
     ms = time_launches(step, args.steps, args.warmup)
     parts = {name: round(time_launches(f, args.steps, 1), 4)
              for name, f in (("appearance_fwd", app_fwd), ("raster_fwd", ras_fwd),
-                             ("raster_bwd", ras_bwd), ("appearance_bwd", app_bwd))}
+                             ("raster_bwd", ras_bwd), ("appearance_bwd", app_bwd),
+                             ("raster_bwd_colour_opacity_only", ras_bwd_colour_only))}
     step()
     torch.cuda.synchronize()
     if int(ws[:4].view(torch.int32).item()) != 0:
@@ -472,7 +479,8 @@ def _training_view(args, log):
     x0, y0, ww, hh = 900, 500, 32, 24
     gwin = torch.zeros_like(gimg)
     gwin[y0:y0 + hh, x0:x0 + ww] = gimg[y0:y0 + hh, x0:x0 + ww]
-    gcw, gow = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gwin, cap)
+    gcw, gow, gmw, gsw, grw = P.raster_bwd(means, scales, rots, opac, rgb[0], cam, ws, gwin, cap,
+                                           geometry=True)
     rgb_np = rgb[0].cpu().numpy()
     p = RR.project(sc.means, sc.scales, sc.rots, sc.cam)
     ex = 3 * np.sqrt(p["cov2"][:, 0, 0]) + 1
@@ -482,7 +490,7 @@ def _training_view(args, log):
     idx = np.nonzero(keep)[0]
     wcam = dict(sc.cam, cx=sc.cam["cx"] - x0, cy=sc.cam["cy"] - y0, width=ww, height=hh)
     ref, scale = RR.render(sc.means[idx], sc.scales[idx], sc.rots[idx], sc.opac[idx], rgb_np[idx],
-                           wcam, grad_image=sc.grad_image[y0:y0 + hh, x0:x0 + ww])
+                           wcam, grad_image=sc.grad_image[y0:y0 + hh, x0:x0 + ww], geometry=True)
     img = state["img"].cpu().numpy()
     par = {"image_window": float(M.scaled_error(img[y0:y0 + hh, x0:x0 + ww], ref["image"],
                                                 scale["image"]).max()),
@@ -490,6 +498,12 @@ def _training_view(args, log):
                                                       scale["colors"]).max()),
            "grad_opac_window": float(M.scaled_error(gow.cpu().numpy()[idx], ref["opac"],
                                                     scale["opac"]).max()),
+           "grad_means_window": float(M.scaled_error(gmw.cpu().numpy()[idx], ref["means"],
+                                                     scale["means"]).max()),
+           "grad_scales_window": float(M.scaled_error(gsw.cpu().numpy()[idx], ref["scales"],
+                                                      scale["scales"]).max()),
+           "grad_rots_window": float(M.scaled_error(grw.cpu().numpy()[idx], ref["rots"],
+                                                    scale["rots"]).max()),
            "window_primitives": int(len(idx))}
     sidx = np.sort(np.random.default_rng(0).choice(n, size=256, replace=False))
     sub = W.take_primitives(w, sidx)
@@ -507,7 +521,7 @@ def _training_view(args, log):
     tiles = ((width + 15) // 16) * ((height + 15) // 16)
     # dominant kernel: the compositing backward (raster_bwd = accumulator clear,
     # raster_render_bwd, rounding to float32; the two small kernels take ~0.5 %)
-    counters = measured_counters(f"raster_render_bwd_n{n}_{width}x{height}", RASTER_SOURCES)
+    counters = measured_counters(f"raster_render_bwd_geom_n{n}_{width}x{height}", RASTER_SOURCES)
     roofline = None
     if counters is not None:
         lane_ops = counters["valu_wave_instructions_per_launch"] * 64
@@ -517,10 +531,11 @@ def _training_view(args, log):
                     "unit": "T VALU lane-instructions/s",
                     "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
                     "traffic": counters["bytes_per_launch"],
-                    "kernel": "raster_render_bwd (compositing backward)"}
+                    "kernel": "raster_render_bwd (compositing backward with geometry)"}
     return dict(value=round(n / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32 (f64 compositing sums)",
                 config={"workload": f"one training view: NASGabor K={k} colours of {n} primitives for "
-                                    f"one camera, composited into {width}x{height}, compositing and "
+                                    f"one camera, composited into {width}x{height}, compositing "
+                                    f"backward (colour, opacity and geometry gradients) and "
                                     f"appearance backward ({args.norm} normaliser)",
                         "primitives": n, "lobes": k, "views": 1, "width": width, "height": height,
                         "tile_capacity": cap, "tiles": tiles},
