@@ -653,7 +653,10 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
       const double A = s.a * dx * dx, B = s.b2 * dx;
       double gc0 = 0.0, gc1 = 0.0, gc2 = 0.0;
       float gop = 0.f;
-      double gu = 0.0, gv = 0.0, ga = 0.0, gb = 0.0, gcc = 0.0;  // dL/d(u, v, a, b, c)
+      // geometry: a lane's pixels share dx, so it sums dL/dq, dL/dq dy and
+      // dL/dq dy^2 over them and forms dL/d(u, v, a, b, c) once per entry
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+      const double nhs = -0.5 * static_cast<double>(s.sigma);  // dalpha/dq = -sigma rho / 2
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
         if (RPL > 1 && ((s.mask >> (RPL * m.wave + j)) & 1u) == 0) continue;  // uniform
@@ -678,14 +681,11 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
             const double gs = da * (T * rho);  // dL/dsigma of this pixel
             gop += static_cast<float>(gs);
             if constexpr (GEOM) {
-              // dL/dq = dL/dalpha * sigma * (-rho / 2); q = a dx^2 + 2 b dx dy + c dy^2
-              const double dq = -0.5 * static_cast<double>(s.sigma) * gs;
-              const double hb = 0.5 * s.b2;
-              gu = fma(dq, -2.0 * fma(s.a, dx, hb * dy), gu);
-              gv = fma(dq, -2.0 * fma(hb, dx, s.c * dy), gv);
-              ga = fma(dq, dx * dx, ga);
-              gb = fma(dq, 2.0 * dx * dy, gb);
-              gcc = fma(dq, dy * dy, gcc);
+              const double dq = nhs * gs;  // dL/dq of this pixel
+              const double dqy = dq * dy;
+              q0 += dq;
+              q1 += dqy;
+              q2 = fma(dqy, dy, q2);
             }
           }
           R[j][0] = fma(ald, d0, R[j][0]);
@@ -705,11 +705,13 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
         unsafeAtomicAdd(acc + 3, static_cast<double>(s3));
       }
       if constexpr (GEOM) {
-        const float s4 = wave_sum(static_cast<float>(gu));
-        const float s5 = wave_sum(static_cast<float>(gv));
-        const float s6 = wave_sum(static_cast<float>(ga));
-        const float s7 = wave_sum(static_cast<float>(gb));
-        const float s8 = wave_sum(static_cast<float>(gcc));
+        // q = a dx^2 + b2 dx dy + c dy^2, dx = px - u, dy = py - v
+        const double dq0 = dx * q0;
+        const float s4 = wave_sum(static_cast<float>(-(2.0 * s.a * dq0 + s.b2 * q1)));     // dL/du
+        const float s5 = wave_sum(static_cast<float>(-(s.b2 * dq0 + 2.0 * s.c * q1)));     // dL/dv
+        const float s6 = wave_sum(static_cast<float>(dx * dq0));                            // dL/da
+        const float s7 = wave_sum(static_cast<float>(2.0 * dx * q1));                       // dL/db
+        const float s8 = wave_sum(static_cast<float>(q2));                                  // dL/dc
         if ((threadIdx.x & 63) == 0 && (s4 != 0.f || s5 != 0.f || s6 != 0.f || s7 != 0.f || s8 != 0.f)) {
           double* acc = a.grad_acc + kAccStride * static_cast<int64_t>(s.idx) + 4;
           unsafeAtomicAdd(acc + 0, static_cast<double>(s4));
