@@ -16,6 +16,11 @@
  *
  *     d_{i,v} = (mu_i - o_v) / |mu_i - o_v|        (ray r(t) = o + t d, Section 3.1)
  *
+ * The library also composites per-primitive colours into an image (Section
+ * 3.1: depth-sorted alpha blending of projected 3D Gaussians) with the
+ * gradients of an image loss for colours, opacities and geometry; see the
+ * compositing section at the end of this header.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  * - All array pointers are DEVICE pointers owned by the caller. The library
