@@ -20,6 +20,7 @@ import json
 import multiprocessing as mp
 import os
 import platform
+import re
 import sys
 import time
 
@@ -67,12 +68,20 @@ APPEARANCE_SOURCES = ("capi.hip", "nasg_device.hpp", "nasg_kernels.hip", "nasg_l
 RASTER_SOURCES = ("capi.hip", "nasg_device.hpp", "raster.hpp", "raster_kernels.hip")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines: profiles stay valid
+    across edits that touch only comments."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash(files=APPEARANCE_SOURCES):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_09794_amd", "csrc")
     for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(os.path.basename(f).encode() + fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(os.path.basename(f).encode() + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

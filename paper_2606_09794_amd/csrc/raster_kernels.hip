@@ -1,8 +1,9 @@
 // Compositing of the primitives' colours into an image for one camera
 // (Section 3.1: C = sum_i T_i alpha_i c_i, alpha_i = sigma_i rho_i,
 // T_i = prod_{j<i} (1 - alpha_j)), with the gradients of a loss on the image
-// with respect to the per-primitive colours and opacities, which is what the
-// appearance backward consumes.
+// with respect to the per-primitive colours (what the appearance backward
+// consumes), opacities and, on request, the geometry (mean, scales,
+// quaternion) through rho.
 //
 // The primitives are 3D Gaussians (mean, per-axis scale, quaternion
 // rotation); rho on a pixel's ray is the Gaussian projected onto the image
@@ -38,8 +39,13 @@
 //             and T_i recovered from the forward's final transmittance. Per
 //             primitive, a lane sums its pixels' terms, the wavefront
 //             sums over lanes in registers, and one lane adds the sums to
-//             FP64 per-primitive accumulators with one atomic per value; a
-//             last kernel rounds the accumulators to the float32 outputs.
+//             FP64 per-primitive accumulators with one atomic per value. With
+//             geometry gradients the same pass also sums dL/d(u, v, a, b, c)
+//             (dL/dq = -sigma rho / 2 times the pixel's dL/dalpha);
+//   finish  : per primitive, the accumulators rounded to the float32
+//             outputs and, with geometry gradients, the FP64 chain from
+//             dL/d(u, v, a, b, c) through the projection to the mean, scales
+//             and quaternion.
 #include <hip/hip_runtime.h>
 
 #include "../../include/nasg.h"
