@@ -319,7 +319,8 @@ typedef struct nasg_gaussians {
 
 /* Device bytes of the workspace for n primitives, this camera and capacity
  * (0 for invalid arguments). Layout, each part 256-byte aligned: header
- * (int32 overflow flag at offset 0), tile cursors [tiles] int32, tile lists
+ * (int32 overflow flag at offset 0, int32 stale flag at offset 4, the
+ * forward's sizes from offset 16), tile cursors [tiles] int32, tile lists
  * [tiles][capacity] of 64-bit sort keys, render records [N] (64 B each), bin
  * records [N] (16 B each), the final
  * transmittance per pixel [H][W][2] FP64 (mantissa, power-of-two exponent)
@@ -347,10 +348,14 @@ int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
  * mean, Sigma_2 = M M^T, M = J R_cw R(q/|q|) S and J (FP64 chain per
  * primitive). The support cut, the near plane and the clamp are held fixed
  * (their jumps have no derivative). Camera parameters get no gradient.
- * `workspace` must hold the forward's state for the same inputs and camera:
- * the backward reads the projected primitives, colours and opacities from it
- * (of `g` only the means, scales and rots are read, by the geometry chain)
- * and overwrites only its accumulator part, so it may be repeated.
+ * `workspace` must hold the forward's state for the same inputs, camera and
+ * tile capacity: the backward reads the projected primitives, colours and
+ * opacities from it (of `g` only the means, scales and rots are read, by the
+ * geometry chain) and overwrites only its accumulator part, so it may be
+ * repeated. A workspace holding no forward of the same n, tile grid and
+ * capacity is detected on the device before any list is read: the backward
+ * then computes nothing (every gradient output is zero) and sets the int32 at
+ * byte offset 4 of the workspace nonzero.
  * Per-pixel terms are summed per wavefront in registers and then into FP64
  * per-primitive accumulators with atomics, so the float32 results are
  * reproducible up to the order of those FP64 additions. */

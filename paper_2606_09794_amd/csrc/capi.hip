@@ -209,6 +209,8 @@ int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, co
   a->cap = cap;
   unsigned char* base = static_cast<unsigned char*>(const_cast<void*>(ws));
   a->overflow = reinterpret_cast<int32_t*>(base);
+  a->stale = reinterpret_cast<int32_t*>(base + 4);
+  a->stamp = reinterpret_cast<nasg::RasterStamp*>(base + 16);
   a->cursor = reinterpret_cast<int32_t*>(base + L.cursor_off);
   a->lists = reinterpret_cast<uint64_t*>(base + L.lists_off);
   a->rec = reinterpret_cast<nasg::RenderRec*>(base + L.rec_off);

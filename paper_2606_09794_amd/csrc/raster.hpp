@@ -33,6 +33,16 @@ struct BinRec {
 };
 static_assert(sizeof(BinRec) == 16, "bin record is 16 bytes");
 
+// Written into the workspace header by the forward; the backward checks it
+// before reading any tile list, so a workspace without a forward of the same
+// sizes is never indexed with stale entries.
+struct RasterStamp {
+  uint32_t magic;
+  int32_t cap, tiles_x, tiles_y;
+  int64_t n;
+};
+constexpr uint32_t kStampMagic = 0x4e534731u;
+
 struct RasterArgs {
   const float* means;   // [N][3]
   const float* scales;  // [N][3]
@@ -47,7 +57,9 @@ struct RasterArgs {
   int32_t tiles_x, tiles_y;
   int32_t cap;
   // workspace views
-  int32_t* overflow;
+  int32_t* overflow;    // header byte 0: a tile list overflowed (forward)
+  int32_t* stale;       // header byte 4: the backward found no matching forward
+  RasterStamp* stamp;   // header byte 16
   int32_t* cursor;   // [tiles]
   uint64_t* lists;   // [tiles][cap] keys: float32 depth bits << 32 | primitive index
   RenderRec* rec;    // [N]

@@ -58,14 +58,24 @@ constexpr double kNear = 0.2;
 constexpr float kClamp = 0.99f;
 constexpr double kSupport = 9.0;
 
-__global__ void raster_zero(int32_t* cursor, int64_t n_tiles, int32_t* overflow) {
+__global__ void raster_begin(RasterArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n_tiles) cursor[t] = 0;
-  if (t == 0) *overflow = 0;
+  if (t < static_cast<int64_t>(a.tiles_x) * a.tiles_y) a.cursor[t] = 0;
+  if (t == 0) {
+    *a.overflow = 0;
+    RasterStamp st;
+    st.magic = kStampMagic;
+    st.cap = a.cap;
+    st.tiles_x = a.tiles_x;
+    st.tiles_y = a.tiles_y;
+    st.n = a.n;
+    *a.stamp = st;
+  }
 }
 
-__global__ void raster_zero_acc(double* acc, int64_t n) {
+__global__ void raster_zero_acc(double* acc, int64_t n, int32_t* stale) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i == 0) *stale = 0;
   if (i < n) {
 #pragma unroll
     for (int k = 0; k < kAccStride; ++k) acc[kAccStride * i + k] = 0.0;
@@ -605,6 +615,14 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
   constexpr int kBlock = 256 / RPL;
   __shared__ StageEntry stage[kBlock];
   __shared__ int16_t wlist[kBlock / 64][kBlock];
+  {
+    const RasterStamp st = *a.stamp;  // same for every thread: a uniform exit
+    if (st.magic != kStampMagic || st.cap != a.cap || st.tiles_x != a.tiles_x ||
+        st.tiles_y != a.tiles_y || st.n != a.n) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *a.stale = 1;
+      return;
+    }
+  }
   const int64_t tile = blockIdx.x;
   const TileMap<RPL> m = tile_map<RPL>(a, tile);
   const double cxp = m.px + 0.5;
@@ -738,7 +756,7 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
   const unsigned gt = static_cast<unsigned>((n_tiles + 255) / 256);
   const unsigned gn = static_cast<unsigned>((a.n + 255) / 256);
   if (!bwd) {
-    hipLaunchKernelGGL(raster_zero, dim3(gt), dim3(256), 0, s, a.cursor, n_tiles, a.overflow);
+    hipLaunchKernelGGL(raster_begin, dim3(gt), dim3(256), 0, s, a);
     if (a.n > 0) {
       hipLaunchKernelGGL(raster_project, dim3(gn), dim3(256), 0, s, a);
       hipLaunchKernelGGL(raster_bin, dim3(gn), dim3(256), 0, s, a);
@@ -749,7 +767,7 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
   } else {
     if (a.n == 0) return hipGetLastError();
     const bool geom = a.grad_means != nullptr || a.grad_scales != nullptr || a.grad_rots != nullptr;
-    hipLaunchKernelGGL(raster_zero_acc, dim3(gn), dim3(256), 0, s, a.grad_acc, a.n);
+    hipLaunchKernelGGL(raster_zero_acc, dim3(gn), dim3(256), 0, s, a.grad_acc, a.n, a.stale);
     if (geom) {
       hipLaunchKernelGGL((raster_render_bwd<kBwdRows, true>), dim3(static_cast<unsigned>(n_tiles)),
                          dim3(256 / kBwdRows), 0, s, a);

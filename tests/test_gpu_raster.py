@@ -333,3 +333,26 @@ def test_gradient_descent_lowers_photometric_loss():
         losses.append(float(loss.detach()))
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0], losses[::8]
+
+
+def test_backward_without_matching_forward_computes_nothing():
+    """A backward on a workspace holding no forward of the same sizes (never
+    run, or run with another tile capacity) is caught on the device before any
+    tile list is read: zero gradients and the stale flag set; the matching
+    backward clears the flag."""
+    sc = W.draw_splat_scene(50, 200, 48, 40, scale=(0.05, 0.4))
+    d = _dev(sc)
+    cam = _camera(sc.cam)
+    gi = torch.from_numpy(sc.grad_image).cuda()
+    ws = torch.zeros(P.raster_workspace_bytes(sc.n, cam, 512), dtype=torch.uint8, device="cuda")
+    stale = lambda: int(ws[4:8].view(torch.int32).item())  # noqa: E731
+    out = P.raster_bwd(*d, cam, ws, gi, 512, geometry=True)
+    torch.cuda.synchronize()
+    assert stale() == 1 and all(bool(torch.all(t == 0)) for t in out)
+    P.raster_fwd(*d, cam, 256, workspace=ws)
+    out = P.raster_bwd(*d, cam, ws, gi, 512)
+    torch.cuda.synchronize()
+    assert stale() == 1 and all(bool(torch.all(t == 0)) for t in out)
+    out = P.raster_bwd(*d, cam, ws, gi, 256)
+    torch.cuda.synchronize()
+    assert stale() == 0 and bool(torch.any(out[0] != 0))
