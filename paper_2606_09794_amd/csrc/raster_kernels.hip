@@ -446,6 +446,27 @@ constexpr int kRenormEvery = 32;
 // (half of the float log2 e), so this is the float exponential of -q/2
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 
+// Minimum over the rectangle [x0, x1] x [y0, y1] of the positive definite
+// q = a dx^2 + b2 dx dy + c dy^2 (dx = x - u, dy = y - v): zero if (u, v) is
+// inside; otherwise on the boundary, where each edge is a 1D quadratic
+// minimised at its vertex clamped to the edge.
+__device__ inline double quad_min_rect(double a, double b2, double c, double u, double v,
+                                       double x0, double x1, double y0, double y1) {
+  if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return 0.0;
+  const double hb = 0.5 * b2, ia = 1.0 / a, ic = 1.0 / c;
+  double best = INFINITY;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double dx = (side ? x1 : x0) - u;  // vertical edge
+    const double dy = fmin(fmax(-hb * dx * ic, y0 - v), y1 - v);
+    best = fmin(best, a * dx * dx + b2 * dx * dy + c * dy * dy);
+    const double ey = (side ? y1 : y0) - v;  // horizontal edge
+    const double ex = fmin(fmax(-hb * ey * ia, x0 - u), x1 - u);
+    best = fmin(best, a * ex * ex + b2 * ex * ey + c * ey * ey);
+  }
+  return best;
+}
+
 __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, int e, double x0,
                                    double y0, StageEntry* slot) {
   const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(list[e]));
@@ -462,12 +483,18 @@ __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, in
   s.sigma = r.sigma;
   s.idx = idx;
   s.pad = 0;
+  // a band's bit is set when the ellipse q <= 9 can reach one of its pixel
+  // centres: the box test, then the exact minimum of q over the band's
+  // rectangle of pixel centres (with a relative margin far above rounding)
   uint32_t mask = 0;
   if (r.u + r.ex >= x0 + 0.5 && r.u - r.ex <= x0 + 15.5) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const double ylo = y0 + 4 * b + 0.5, yhi = ylo + 3.0;
-      if (r.v + r.ey >= ylo && r.v - r.ey <= yhi) mask |= 1u << b;
+      if (r.v + r.ey >= ylo && r.v - r.ey <= yhi &&
+          quad_min_rect(r.a, r.b2, r.c, r.u, r.v, x0 + 0.5, x0 + 15.5, ylo, yhi) <=
+              kSupport * (1.0 + 1e-9))
+        mask |= 1u << b;
     }
   }
   s.mask = mask;
