@@ -453,7 +453,7 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 __device__ inline double quad_min_rect(double a, double b2, double c, double u, double v,
                                        double x0, double x1, double y0, double y1) {
   if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return 0.0;
-  const double hb = 0.5 * b2, ia = 1.0 / a, ic = 1.0 / c;
+  const double hb = 0.5 * b2, ia = rcp64(a), ic = rcp64(c);
   double best = INFINITY;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -467,6 +467,10 @@ __device__ inline double quad_min_rect(double a, double b2, double c, double u, 
   return best;
 }
 
+// EXACT adds the exact band test to the box test; it pays in the backward,
+// whose per-entry work is large, not in the forward, where its staging cost
+// outweighs the entries it removes (measured).
+template <bool EXACT>
 __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, int e, double x0,
                                    double y0, StageEntry* slot) {
   const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(list[e]));
@@ -484,7 +488,7 @@ __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, in
   s.idx = idx;
   s.pad = 0;
   // a band's bit is set when the ellipse q <= 9 can reach one of its pixel
-  // centres: the box test, then the exact minimum of q over the band's
+  // centres: the box test and, with EXACT, the minimum of q over the band's
   // rectangle of pixel centres (with a relative margin far above rounding)
   uint32_t mask = 0;
   if (r.u + r.ex >= x0 + 0.5 && r.u - r.ex <= x0 + 15.5) {
@@ -492,8 +496,8 @@ __device__ inline void stage_entry(const RasterArgs& a, const uint64_t* list, in
     for (int b = 0; b < 4; ++b) {
       const double ylo = y0 + 4 * b + 0.5, yhi = ylo + 3.0;
       if (r.v + r.ey >= ylo && r.v - r.ey <= yhi &&
-          quad_min_rect(r.a, r.b2, r.c, r.u, r.v, x0 + 0.5, x0 + 15.5, ylo, yhi) <=
-              kSupport * (1.0 + 1e-9))
+          (!EXACT || quad_min_rect(r.a, r.b2, r.c, r.u, r.v, x0 + 0.5, x0 + 15.5, ylo, yhi) <=
+                         kSupport * (1.0 + 1e-9)))
         mask |= 1u << b;
     }
   }
@@ -591,7 +595,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_fwd(RasterArgs a) {
   for (int base = 0; base < cnt; base += kBlock) {
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
-    if (e < cnt) stage_entry(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
+    if (e < cnt) stage_entry<false>(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
     __syncthreads();
     const int nl = wave_compact(stage, min(kBlock, cnt - base), bits, wl);
     __syncthreads();
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
     const int base = max(0, end - kBlock);
     __syncthreads();
     const int e = base + static_cast<int>(threadIdx.x);
-    if (e < end) stage_entry(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
+    if (e < end) stage_entry<true>(a, list, e, m.x0, m.y0, &stage[threadIdx.x]);
     __syncthreads();
     const int nl = wave_compact(stage, end - base, bits, wl);
     __syncthreads();
