@@ -348,6 +348,8 @@ def raster_fwd(means, scales, rots, opac, colors, cam: Camera, tile_capacity: in
     g = _gaussians(means, scales, rots, opac, colors)
     cs = cam.struct()
     nb = raster_workspace_bytes(g.n, cam, tile_capacity)
+    if workspace is not None:
+        _dev(workspace, "workspace", torch.uint8)   # its numel() is its size in bytes
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(nb, dtype=torch.uint8, device=means.device)
     img = torch.empty(cam.height, cam.width, 3, dtype=torch.float32, device=means.device)
@@ -368,6 +370,9 @@ def raster_bwd(means, scales, rots, opac, colors, cam: Camera, workspace, grad_i
     g = _gaussians(means, scales, rots, opac, colors)
     cs = cam.struct()
     _dev(grad_image, "grad_image")
+    _dev(workspace, "workspace", torch.uint8)
+    if tuple(grad_image.shape) != (cam.height, cam.width, 3):
+        raise ValueError(f"grad_image must have shape {(cam.height, cam.width, 3)}")
     gc = torch.empty_like(colors)
     go = torch.empty_like(opac)
     geo = [torch.empty_like(t) for t in (means, scales, rots)] if geometry else [None] * 3
