@@ -12,6 +12,16 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
 
 
+def pytest_sessionstart(session):
+    """Build libnasg.so (hipcc cross-compiles for gfx950) only when no built
+    library is present, e.g. on a fresh checkout; an existing build is used
+    as it is."""
+    from paper_2606_09794_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_09794_amd import build
+        build.build()
+
+
 @pytest.fixture(scope="session")
 def repo_root():
     return ROOT
