@@ -179,3 +179,50 @@ def test_autograd_function():
     for k in ("quat", "shape", "rgbw", "c0"):
         compare(leaves[k].grad.cpu().numpy(), ref[k], scale[k], k, TOL)
     compare(leaves["means"].grad.cpu().numpy(), ref["geom"], scale["geom"], "means", TOL)
+
+
+def test_eval_calls_replay_from_a_graph():
+    """The single-scene calls allocate, copy and synchronise nothing:
+    nasg_eval_fwd, nasg_eval_bwd (fused) and the SH pair captured into one
+    graph replay bitwise equal to the eager run (they use no atomics), with
+    eager work and poisoned outputs between replays."""
+    w = W.draw_workload(61, 3000, 8, 16)
+    d = upload(w)
+    g = P.nasg_grad_buffers(w.k, w.n, "cuda")
+    rgb = torch.empty_like(d["grad_rgb"])
+    rgb2 = torch.empty_like(d["grad_rgb"])
+    rgb_sh = torch.empty_like(d["grad_rgb"])
+    gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((w.n, 3), device="cuda")}
+    outs = [rgb, rgb2, rgb_sh, *g.values(), *gsh.values()]
+
+    def run():
+        P.nasg_eval_fwd(d["quat"], d["shape"], d["rgbw"], d["c0"], means=d["means"],
+                        cams=d["cams"], out=rgb)
+        P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],
+                        means=d["means"], cams=d["cams"], grads=g, rgb_out=rgb2)
+        P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"], grads=gsh,
+                       rgb_out=rgb_sh)
+
+    run()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in outs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(float("nan"))
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for k, (t, e) in enumerate(zip(outs, eager)):
+            assert torch.equal(t, e), (rep, k)
