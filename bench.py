@@ -66,6 +66,8 @@ def sh_bytes(n, v, *, fwd=True, bwd=True):
 APPEARANCE_SOURCES = ("capi.hip", "nasg_device.hpp", "nasg_kernels.hip", "nasg_launch.hpp",
                       "nasg_skeleton.hpp", "../tuning_gfx950.json")
 RASTER_SOURCES = ("capi.hip", "nasg_device.hpp", "raster.hpp", "raster_kernels.hip")
+SH_SOURCES = ("capi.hip", "nasg_device.hpp", "nasg_launch.hpp", "sh3_kernels.hip",
+              "../tuning_gfx950.json")
 
 
 def _code_only(text: str) -> str:
@@ -562,6 +564,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (no comparisons, no CPU leg)")
     ap.add_argument("--cpu-prims", type=int, default=3_000_000,
                     help="primitives in the CPU-oracle timing sample")
+    ap.add_argument("--profile-kernel", choices=["nasg", "sh3"], default="nasg",
+                    help="with --profile: the headline NASGabor launch (plus the copy "
+                         "calibration) or the degree-3 SH fused launch on the same inputs")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a few headline launches plus a plain "
                          "device copy of --copy-mib MiB for calibrating byte counters")
@@ -609,6 +614,16 @@ def main():
                         cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
 
     if args.profile:
+        if args.profile_kernel == "sh3":
+            gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
+            for _ in range(args.steps):
+                P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"], grads=gsh,
+                               rgb_out=rgb)
+            torch.cuda.synchronize()
+            print(json.dumps({"profile": True, "kernel": "sh3 fused", "launches": args.steps,
+                              "n": n, "v": v, "algorithmic_bytes_per_launch": sh_bytes(n, v),
+                              "source_hash": kernel_source_hash(SH_SOURCES)}), flush=True)
+            return
         for _ in range(args.steps):
             fused()
         src = torch.empty(args.copy_mib << 18, device="cuda")        # float32 elements
