@@ -59,26 +59,37 @@ __device__ inline void sh_basis(float x, float y, float z, float Y[16]) {
   Y[15] = -c3a * x * (xx - 3.f * yy);
 }
 
-// sum_j b[j] grad Y_j(x, y, z) of the homogeneous polynomials
+// sum_j b[j] grad Y_j(x, y, z) of the homogeneous polynomials: the weighted
+// sum is first collected into one polynomial over the monomials of (x, y, z)
+// (the basis expansions above, term by term), which is then differentiated.
 __device__ inline void sh_grad(float x, float y, float z, const float b[16], float& gx,
                                float& gy, float& gz) {
   using namespace shc;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  gx = -c1 * b[3];
-  gy = -c1 * b[1];
-  gz = c1 * b[2];
-  gx += c2a * (y * b[4] - z * b[7]) - 2.f * c2b * x * b[6] + 2.f * c2c * x * b[8];
-  gy += c2a * (x * b[4] - z * b[5]) - 2.f * c2b * y * b[6] - 2.f * c2c * y * b[8];
-  gz += -c2a * (y * b[5] + x * b[7]) + 4.f * c2b * z * b[6];
-  gx += -c3a * 6.f * x * y * b[9] + c3b * y * z * b[10] + c3c * 2.f * x * y * b[11] -
-        c3d * 6.f * x * z * b[12] - c3c * (4.f * zz - 3.f * xx - yy) * b[13] +
-        c3e * 2.f * x * z * b[14] - c3a * (3.f * xx - 3.f * yy) * b[15];
-  gy += -c3a * (3.f * xx - 3.f * yy) * b[9] + c3b * x * z * b[10] -
-        c3c * (4.f * zz - xx - 3.f * yy) * b[11] - c3d * 6.f * y * z * b[12] +
-        c3c * 2.f * x * y * b[13] - c3e * 2.f * y * z * b[14] + c3a * 6.f * x * y * b[15];
-  gz += c3b * x * y * b[10] - c3c * 8.f * y * z * b[11] +
-        c3d * (6.f * zz - 3.f * xx - 3.f * yy) * b[12] - c3c * 8.f * x * z * b[13] +
-        c3e * (xx - yy) * b[14];
+  // degree 1
+  const float Lx = -c1 * b[3], Ly = -c1 * b[1], Lz = c1 * b[2];
+  // degree 2; the squares' coefficients carry their derivative factor 2
+  const float Qxy = c2a * b[4], Qyz = -c2a * b[5], Qxz = -c2a * b[7];
+  const float Qxx2 = 2.f * (c2c * b[8] - c2b * b[6]);
+  const float Qyy2 = -2.f * (c2b * b[6] + c2c * b[8]);
+  const float Qzz2 = 4.f * c2b * b[6];
+  // degree 3, one coefficient per monomial
+  const float Cxxy = c3c * b[11] - 3.f * c3a * b[9];
+  const float Cyyy = c3a * b[9] + c3c * b[11];
+  const float Cxyz = c3b * b[10];
+  const float Cyzz = -4.f * c3c * b[11];
+  const float Czzz = 2.f * c3d * b[12];
+  const float Cxxz = c3e * b[14] - 3.f * c3d * b[12];
+  const float Cyyz = -(3.f * c3d * b[12] + c3e * b[14]);
+  const float Cxzz = -4.f * c3c * b[13];
+  const float Cxxx = c3c * b[13] - c3a * b[15];
+  const float Cxyy = c3c * b[13] + 3.f * c3a * b[15];
+  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+  gx = Lx + Qxy * y + Qxz * z + Qxx2 * x + 2.f * Cxxy * xy + Cxyz * yz + 2.f * Cxxz * xz +
+       Cxzz * zz + 3.f * Cxxx * xx + Cxyy * yy;
+  gy = Ly + Qxy * x + Qyz * z + Qyy2 * y + Cxxy * xx + 3.f * Cyyy * yy + Cxyz * xz +
+       Cyzz * zz + 2.f * Cyyz * yz + 2.f * Cxyy * xy;
+  gz = Lz + Qyz * y + Qxz * x + Qzz2 * z + Cxyz * xy + 2.f * Cyzz * yz + 3.f * Czzz * zz +
+       Cxxz * xx + Cyyz * yy + 2.f * Cxzz * xz;
 }
 
 template <int P, int VPL, bool BWD>
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
         e1 -= a.cams[3 * v + 1];
         e2 -= a.cams[3 * v + 2];
       }
-      const float ri = 1.f / sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+      const float ri = rsqrtf(e0 * e0 + e1 * e1 + e2 * e2);
       const float x = e0 * ri, y = e1 * ri, z = e2 * ri;
       float Y[16];
       sh_basis(x, y, z, Y);
