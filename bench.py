@@ -172,6 +172,20 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def copy_ceiling(steps, mib=1024):
+    """The achievable HBM rate beside the 8 TB/s spec: a plain device-to-device
+    copy of `mib` MiB (the runtime's copy kernel), each byte read once and
+    written once."""
+    import torch
+    src = torch.empty(mib << 18, device="cuda")
+    dst = torch.empty_like(src)
+    ms = time_launches(lambda: dst.copy_(src), steps, 1)
+    cb = 2 * src.numel() * 4
+    del src, dst
+    return {"ms": round(ms, 4), "bytes": cb, "GB_s": round(cb / ms / 1e6, 1),
+            "frac_of_peak": round(cb / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
 def sampled_parity(w, d, g, rgb, norm, n_sample=512, seed=0):
     """Oracle on sampled primitives of the full-size run (all views, all lobes)."""
     import workloads as W
@@ -252,8 +266,12 @@ def bench_other(args, log):
                              "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
                              "traffic": None, "algorithmic_bytes_per_launch": ab},
                    compare={"sh3_fused": {"ms": round(msh, 4), "G_evals_s": round(n * v / msh / 1e6, 4),
-                                          "hbm_frac": round(sh_bytes(n, v) / msh / 1e6 / HBM_PEAK_GBS, 4)}},
+                                          "hbm_frac": round(sh_bytes(n, v) / msh / 1e6 / HBM_PEAK_GBS, 4)},
+                            "hbm_copy_ceiling": copy_ceiling(args.steps)},
                    parity_sampled_max_scaled_error=_sampled(w, dict(g, rgb=rgb), args.norm))
+        rf = res["roofline"]
+        rf["copy_ceiling_GB_s"] = res["compare"]["hbm_copy_ceiling"]["GB_s"]
+        rf["frac_of_copy_ceiling"] = round(rf["achieved"] / rf["copy_ceiling_GB_s"], 4)
     elif args.workload == "bf16-k16":
         w = W.config3(n=args.n)
         log(f"generated N={w.n} K={w.k} V={w.v} bf16")
@@ -718,6 +736,10 @@ def main():
         cmp["nasg_plain_single_view"] = {"ms": round(m, 4), "G_evals_s": round(n / m / 1e6, 4),
                                          "GB_s": round(pb / m / 1e6, 1),
                                          "hbm_frac": round(pb / m / 1e6 / HBM_PEAK_GBS, 4)}
+        cmp["hbm_copy_ceiling"] = copy_ceiling(steps)
+        hb = out["roofline"].get("hbm", out["roofline"])
+        hb["copy_ceiling_GB_s"] = cmp["hbm_copy_ceiling"]["GB_s"]
+        hb["frac_of_copy_ceiling"] = round(hb["achieved"] / cmp["hbm_copy_ceiling"]["GB_s"], 4)
         out["compare"] = cmp
         # sampled parity of the timed configuration (rerun the headline once)
         fused()
