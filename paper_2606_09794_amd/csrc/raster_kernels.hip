@@ -57,6 +57,9 @@ namespace nasg {
 constexpr double kNear = 0.2;
 constexpr float kClamp = 0.99f;
 constexpr double kSupport = 9.0;
+constexpr int kBinParts = 8;  // tile classes of the binning pass, one per XCD
+constexpr int kBinLdsTiles = 8192;      // class tiles one LDS-counting block holds
+constexpr int kBinPrimsPerThread = 32;  // primitives per thread of an LDS-counting block
 
 __global__ void raster_begin(RasterArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -273,33 +276,103 @@ __device__ inline uint64_t depth_key(double z, int64_t i) {
          static_cast<uint32_t>(i);
 }
 
-// Appends each primitive's key to the lists of the tiles its box touches. The
-// cursor atomics of up to eight tiles are issued before their results are
-// used, so their latencies overlap.
+// Tile binning. Each of the chip's eight XCDs has its own L2 and workgroups
+// go to them in turn, so a list line filled from several XCDs reaches HBM as
+// several partial-line writes. The tiles are therefore split into eight
+// classes (tile index mod 8) and block b serves class b mod 8 for the
+// primitives of chunk b / 8: every list is written from one XCD, whose L2
+// merges its lines. The order of appends does not matter: the per-tile sort
+// orders each list by its keys.
+
+// Calls f(tile) for each tile of box r in class `part`: in each row, the
+// box's columns whose tile index is part mod kBinParts.
+template <class F>
+__device__ inline void for_class_tiles(const BinRec& r, int64_t tiles_x, int part, F&& f) {
+  for (int y = r.ty0; y <= r.ty1; ++y) {
+    const int64_t row = static_cast<int64_t>(y) * tiles_x;
+    for (int tx = r.tx0 + static_cast<int>((part - (row + r.tx0)) & (kBinParts - 1)); tx <= r.tx1;
+         tx += kBinParts)
+      f(row + tx);
+  }
+}
+
+// Images of up to kBinParts * kBinLdsTiles tiles. A block first counts its
+// chunk's entries per class tile in LDS, then reserves each touched tile's
+// range in its list with one device atomic on the tile's cursor, then places
+// the keys in those ranges with LDS atomics: one device atomic per (block,
+// tile) instead of one per entry.
+__global__ __launch_bounds__(256) void raster_bin_lds(RasterArgs a) {
+  __shared__ int cnt[kBinLdsTiles];
+  const int part = static_cast<int>(blockIdx.x & (kBinParts - 1));
+  const int64_t first = static_cast<int64_t>(blockIdx.x / kBinParts) * (256 * kBinPrimsPerThread);
+  const int64_t last = min(first + 256 * kBinPrimsPerThread, a.n);
+  const int64_t n_tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
+  const int n_local = static_cast<int>((n_tiles - part + kBinParts - 1) / kBinParts);
+  for (int m = threadIdx.x; m < n_local; m += 256) cnt[m] = 0;
+  __syncthreads();
+  for (int64_t i = first + threadIdx.x; i < last; i += 256) {
+    const BinRec r = a.bins[i];
+    for_class_tiles(r, a.tiles_x, part, [&](int64_t t) { atomicAdd(&cnt[t / kBinParts], 1); });
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < n_local; m += 256) {
+    const int c = cnt[m];
+    if (c > 0) cnt[m] = atomicAdd(a.cursor + static_cast<int64_t>(m) * kBinParts + part, c);
+  }
+  __syncthreads();
+  for (int64_t i = first + threadIdx.x; i < last; i += 256) {
+    const BinRec r = a.bins[i];
+    const uint64_t key = depth_key(r.z, i);
+    for_class_tiles(r, a.tiles_x, part, [&](int64_t t) {
+      const int pos = atomicAdd(&cnt[t / kBinParts], 1);
+      if (pos < a.cap) {
+        a.lists[t * a.cap + pos] = key;
+      } else {
+        atomicMax(a.overflow, 1);
+      }
+    });
+  }
+}
+
+// Larger images: one device atomic per entry on the tile's cursor, those of
+// up to eight tiles issued before their results are used, so their latencies
+// overlap. Slot (row y, j) of a box is column first(y) + kBinParts * j, where
+// first(y) is the box's first column in this class.
 __global__ void raster_bin(RasterArgs a) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int part = static_cast<int>(blockIdx.x & (kBinParts - 1));
+  const int64_t i = static_cast<int64_t>(blockIdx.x / kBinParts) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const BinRec r = a.bins[i];
   const int w = r.tx1 - r.tx0 + 1, h = r.ty1 - r.ty0 + 1;
   if (w <= 0 || h <= 0) return;
-  const int area = w * h;
+  const int cw = (w + kBinParts - 1) / kBinParts;
+  const int slots = cw * h;
   const uint64_t key = depth_key(r.z, i);
-  for (int k0 = 0; k0 < area; k0 += 8) {
+  for (int k0 = 0; k0 < slots; k0 += 8) {
     int64_t tl[8];
     int32_t pos[8];
+    bool use[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u;
       tl[u] = 0;
       pos[u] = 0;
-      if (k < area) {
-        tl[u] = static_cast<int64_t>(r.ty0 + k / w) * a.tiles_x + (r.tx0 + k % w);
-        pos[u] = atomicAdd(a.cursor + tl[u], 1);
+      use[u] = false;
+      if (k < slots) {
+        const int y = r.ty0 + k / cw;
+        const int64_t row = static_cast<int64_t>(y) * a.tiles_x;
+        const int lead = static_cast<int>((part - (row + r.tx0)) & (kBinParts - 1));
+        const int tx = r.tx0 + lead + kBinParts * (k % cw);
+        if (tx <= r.tx1) {
+          use[u] = true;
+          tl[u] = row + tx;
+          pos[u] = atomicAdd(a.cursor + tl[u], 1);
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (k0 + u < area) {
+      if (use[u]) {
         if (pos[u] < a.cap) {
           a.lists[tl[u] * a.cap + pos[u]] = key;
         } else {
@@ -790,7 +863,13 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
     hipLaunchKernelGGL(raster_begin, dim3(gt), dim3(256), 0, s, a);
     if (a.n > 0) {
       hipLaunchKernelGGL(raster_project, dim3(gn), dim3(256), 0, s, a);
-      hipLaunchKernelGGL(raster_bin, dim3(gn), dim3(256), 0, s, a);
+      if ((n_tiles + kBinParts - 1) / kBinParts <= kBinLdsTiles) {
+        const int64_t chunk = 256 * kBinPrimsPerThread;
+        const unsigned gc = static_cast<unsigned>((a.n + chunk - 1) / chunk);
+        hipLaunchKernelGGL(raster_bin_lds, dim3(gc * kBinParts), dim3(256), 0, s, a);
+      } else {
+        hipLaunchKernelGGL(raster_bin, dim3(gn * kBinParts), dim3(256), 0, s, a);
+      }
     }
     hipLaunchKernelGGL(raster_sort, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(raster_render_fwd<kFwdRows>, dim3(static_cast<unsigned>(n_tiles)),

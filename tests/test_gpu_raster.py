@@ -302,6 +302,28 @@ def test_widest_image_on_windows():
             compare(v[idx], ref[name], scale[name], f"grad {name} x0={x0}", TOL)
 
 
+def test_many_tiles_on_windows():
+    """An 8192 x 4352 image (512 x 272 = 139 264 tiles, more than the binning
+    pass counts per tile class in LDS, so it takes the per-entry path) with
+    400 000 primitives: windows at two corners and inside against the oracle."""
+    width, height = 8192, 4352
+    sc = W.draw_splat_scene(33, 400_000, width, height, scale=(1e-3, 1e-2))
+    img, gc, go = _gpu(sc, cap=1024)
+    for x0, y0 in ((0, 0), (3000, 2100), (width - 64, height - 48)):
+        w, h = 64, 48
+        g = np.zeros_like(sc.grad_image)
+        g[y0:y0 + h, x0:x0 + w] = sc.grad_image[y0:y0 + h, x0:x0 + w]
+        img_w, gc_w, go_w, gm_w, gs_w, gr_w = _gpu(sc, cap=1024, grad_image=g, geometry=True)
+        idx, ref, scale = _window_oracle(sc, x0, y0, w, h)
+        assert len(idx) > 20
+        at = f"x0={x0} y0={y0}"
+        compare(img[y0:y0 + h, x0:x0 + w], ref["image"], scale["image"], f"image window {at}", TOL)
+        compare(gc_w[idx], ref["colors"], scale["colors"], f"grad colors {at}", TOL)
+        compare(go_w[idx], ref["opac"], scale["opac"], f"grad opac {at}", TOL)
+        for name, v in zip(GEOM, (gm_w, gs_w, gr_w)):
+            compare(v[idx], ref[name], scale[name], f"grad {name} {at}", TOL)
+
+
 def test_gradient_descent_lowers_photometric_loss():
     """The gradients train: from a perturbed copy of a scene (lobes, c0,
     opacities, means, scales, rotations), Adam on the squared difference to
