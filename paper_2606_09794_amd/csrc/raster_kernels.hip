@@ -495,16 +495,63 @@ struct StageEntry {
   int32_t pad;
 };
 
-// Sum over the 64 lanes of a wavefront (every lane active): DPP row sums;
-// row_bcast:15 adds row 0's sum into row 1 and row 2's into row 3;
-// row_bcast:31 adds lane 31 (rows 0 + 1) into rows 2 and 3; lane 63 then
-// holds the total, read out as a uniform value.
-__device__ inline float wave_sum(float x) {
-  x = group_sum<16>(x);
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, false));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+// Totals of several per-lane values over the 64 lanes of a wavefront (every
+// lane active) by halving exchanges: at each step a lane keeps half of the
+// values it holds, adds its partner's partial sums of that half and passes
+// the other half on, so the totals end up spread over the lanes instead of
+// being reduced one value at a time. Partners: lane ^ 32 and lane ^ 16 (the
+// permlane swaps), lane ^ 1 and lane ^ 2 (quad DPP); lane bits 2 and 3 are
+// then summed with row rotations by 8 and 4.
+__device__ inline float swap32_sum(float x, float y) {
+  // lanes 0-31: x[l] + x[l + 32]; lanes 32-63: y[l - 32] + y[l]
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+
+__device__ inline float swap16_sum(float x, float y) {
+  // rows 0 and 2 (lane bit 4 clear): x[l] + x[l ^ 16]; rows 1 and 3: y[l ^ 16] + y[l]
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kRowRor8 = 0x128;
+constexpr int kRowRor4 = 0x124;
+
+// Nine values: lane l ends with the total of value lane_slot9(l); lanes 0, 1,
+// 2, 16, 17, 32, 33, 48, 49 hold the nine totals once each.
+__device__ inline float lane_sums9(const float (&x)[9], int lane) {
+  const float a0 = swap32_sum(x[0], x[1]), a1 = swap32_sum(x[2], x[3]);
+  const float a2 = swap32_sum(x[4], x[5]), a3 = swap32_sum(x[6], x[7]);
+  const float a4 = swap32_sum(x[8], x[8]);
+  const float b0 = swap16_sum(a0, a1), b1 = swap16_sum(a2, a3), b2 = swap16_sum(a4, a4);
+  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0;
+  const float c0 = (o1 ? b1 : b0) + dpp_f<kQuadXor1>(o1 ? b0 : b1);
+  const float c1 = b2 + dpp_f<kQuadXor1>(b2);
+  float d = (o2 ? c1 : c0) + dpp_f<kQuadXor2>(o2 ? c0 : c1);
+  d += dpp_f<kRowRor8>(d);
+  d += dpp_f<kRowRor4>(d);
+  return d;
+}
+__device__ inline bool lane_writes9(int lane) { return (lane & 0xE) == 0 || lane == 2; }
+__device__ inline int lane_slot9(int lane) {
+  return lane == 2 ? 8 : 4 * (lane & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+}
+
+// Four values: lanes 0, 16, 32, 48 hold the totals of values 0, 2, 1, 3.
+__device__ inline float lane_sums4(const float (&x)[4]) {
+  float b = swap16_sum(swap32_sum(x[0], x[1]), swap32_sum(x[2], x[3]));
+  b += dpp_f<kQuadXor1>(b);
+  b += dpp_f<kQuadXor2>(b);
+  b += dpp_f<kRowRor8>(b);
+  b += dpp_f<kRowRor4>(b);
+  return b;
+}
+__device__ inline bool lane_writes4(int lane) { return (lane & 0xF) == 0; }
+__device__ inline int lane_slot4(int lane) { return 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1); }
 
 // Transmittance as t * 2^E (E a multiple of kRenorm). t is renormalised every
 // kRenormEvery entries of a wavefront's list and at the end of each chunk, so
@@ -767,6 +814,9 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
       }
     }
   };
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  const bool writer = GEOM ? lane_writes9(lane) : lane_writes4(lane);
+  const int slot = GEOM ? lane_slot9(lane) : lane_slot4(lane);
   for (int end = cnt; end > 0; end -= kBlock) {
     const int base = max(0, end - kBlock);
     __syncthreads();
@@ -821,34 +871,27 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
           R[j][2] = fma(ald, d2, R[j][2]);
         }
       }
-      const float s0 = wave_sum(static_cast<float>(gc0));
-      const float s1 = wave_sum(static_cast<float>(gc1));
-      const float s2 = wave_sum(static_cast<float>(gc2));
-      const float s3 = wave_sum(gop);
-      if ((threadIdx.x & 63) == 0 && (s0 != 0.f || s1 != 0.f || s2 != 0.f || s3 != 0.f)) {
-        double* acc = a.grad_acc + kAccStride * static_cast<int64_t>(s.idx);
-        unsafeAtomicAdd(acc + 0, static_cast<double>(s0));
-        unsafeAtomicAdd(acc + 1, static_cast<double>(s1));
-        unsafeAtomicAdd(acc + 2, static_cast<double>(s2));
-        unsafeAtomicAdd(acc + 3, static_cast<double>(s3));
-      }
+      // the entry's totals over the wavefront, one per writing lane
+      float tot;
       if constexpr (GEOM) {
         // q = a dx^2 + b2 dx dy + c dy^2, dx = px - u, dy = py - v
         const double dq0 = dx * q0;
-        const float s4 = wave_sum(static_cast<float>(-(2.0 * s.a * dq0 + s.b2 * q1)));     // dL/du
-        const float s5 = wave_sum(static_cast<float>(-(s.b2 * dq0 + 2.0 * s.c * q1)));     // dL/dv
-        const float s6 = wave_sum(static_cast<float>(dx * dq0));                            // dL/da
-        const float s7 = wave_sum(static_cast<float>(2.0 * dx * q1));                       // dL/db
-        const float s8 = wave_sum(static_cast<float>(q2));                                  // dL/dc
-        if ((threadIdx.x & 63) == 0 && (s4 != 0.f || s5 != 0.f || s6 != 0.f || s7 != 0.f || s8 != 0.f)) {
-          double* acc = a.grad_acc + kAccStride * static_cast<int64_t>(s.idx) + 4;
-          unsafeAtomicAdd(acc + 0, static_cast<double>(s4));
-          unsafeAtomicAdd(acc + 1, static_cast<double>(s5));
-          unsafeAtomicAdd(acc + 2, static_cast<double>(s6));
-          unsafeAtomicAdd(acc + 3, static_cast<double>(s7));
-          unsafeAtomicAdd(acc + 4, static_cast<double>(s8));
-        }
+        const float v[9] = {static_cast<float>(gc0), static_cast<float>(gc1),
+                            static_cast<float>(gc2), gop,
+                            static_cast<float>(-(2.0 * s.a * dq0 + s.b2 * q1)),  // dL/du
+                            static_cast<float>(-(s.b2 * dq0 + 2.0 * s.c * q1)),  // dL/dv
+                            static_cast<float>(dx * dq0),                        // dL/da
+                            static_cast<float>(2.0 * dx * q1),                   // dL/db
+                            static_cast<float>(q2)};                             // dL/dc
+        tot = lane_sums9(v, lane);
+      } else {
+        const float v[4] = {static_cast<float>(gc0), static_cast<float>(gc1),
+                            static_cast<float>(gc2), gop};
+        tot = lane_sums4(v);
       }
+      if (writer && tot != 0.f)
+        unsafeAtomicAdd(a.grad_acc + kAccStride * static_cast<int64_t>(s.idx) + slot,
+                        static_cast<double>(tot));
       if ((i & (kRenormEvery - 1)) == 0) renorm();
     }
     renorm();
