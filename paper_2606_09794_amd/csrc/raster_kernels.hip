@@ -430,22 +430,12 @@ __device__ void bitonic_keys(uint64_t (&v)[EPT], uint64_t* lds) {
   }
 }
 
-template <int EPT>
-__device__ void sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t* lds) {
+// Runs of equal float depth (in index order on entry): a stable insertion
+// sort by FP64 depth, done by the thread that owns the run's first entry;
+// then the sorted keys go back to the tile's list.
+__device__ void order_runs_and_store(const RasterArgs& a, uint64_t* list, int cnt,
+                                     uint64_t* lds) {
   const int t = static_cast<int>(threadIdx.x);
-  // coalesced load through LDS into the blocked register layout
-  for (int e = t; e < 256 * EPT; e += 256) lds[e] = e < cnt ? list[e] : ~0ull;
-  __syncthreads();
-  uint64_t v[EPT];
-#pragma unroll
-  for (int r = 0; r < EPT; ++r) v[r] = lds[t * EPT + r];
-  bitonic_keys<EPT>(v, lds);
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
-  __syncthreads();
-  // runs of equal float depth (already in index order): a stable insertion
-  // sort by FP64 depth, done by the thread that owns the run's first entry
   for (int e = t; e < cnt; e += 256) {
     const uint32_t hi = static_cast<uint32_t>(lds[e] >> 32);
     const bool start = e == 0 || static_cast<uint32_t>(lds[e - 1] >> 32) != hi;
@@ -467,14 +457,136 @@ __device__ void sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t
   for (int e = t; e < cnt; e += 256) list[e] = lds[e];
 }
 
+template <int EPT>
+__device__ void sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t* lds) {
+  const int t = static_cast<int>(threadIdx.x);
+  // coalesced load through LDS into the blocked register layout
+  for (int e = t; e < 256 * EPT; e += 256) lds[e] = e < cnt ? list[e] : ~0ull;
+  __syncthreads();
+  uint64_t v[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) v[r] = lds[t * EPT + r];
+  bitonic_keys<EPT>(v, lds);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) lds[t * EPT + r] = v[r];
+  __syncthreads();
+  order_runs_and_store(a, list, cnt, lds);
+}
+
+// Bucket sort of one tile's keys (257 .. 4096 of them) on the float depth
+// bits, which order like the depths: bucket (bits - min) >> shift, with the
+// shift that fits the tile's span of bits into kSortBuckets buckets, is
+// monotone in the key, so sorting each bucket by the full key (depth bits,
+// then index) sorts the list. An LDS histogram, a block scan of it and a
+// scatter place the keys; the owner of 16 consecutive buckets then sorts
+// each of them by insertion. Returns false, having changed nothing, when a
+// bucket holds more than kSortBucketRun keys: the bitonic network takes
+// that tile instead.
+constexpr int kSortBuckets = 4096;
+constexpr int kSortBucketRun = 32;
+
+__device__ bool bucket_sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t* out,
+                                 int* bucket, uint32_t* red) {
+  constexpr int R = 16;  // keys per thread at the most: 4096 = 256 x 16
+  constexpr int BPT = kSortBuckets / 256;
+  const int t = static_cast<int>(threadIdx.x), lane = t & 63, wave = t >> 6;
+  uint64_t key[R];
+  uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = t + 256 * r;
+    key[r] = 0;
+    if (e < cnt) {
+      key[r] = list[e];
+      const uint32_t h = static_cast<uint32_t>(key[r] >> 32);
+      lo = min(lo, h);
+      hi = max(hi, h);
+    }
+  }
+  for (int k = t; k < kSortBuckets; k += 256) bucket[k] = 0;
+  for (int o = 32; o >= 1; o >>= 1) {
+    lo = min(lo, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), o, 64)));
+    hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, 64)));
+  }
+  if (lane == 0) {
+    red[wave] = lo;
+    red[4 + wave] = hi;
+  }
+  __syncthreads();
+  lo = min(min(red[0], red[1]), min(red[2], red[3]));
+  hi = max(max(red[4], red[5]), max(red[6], red[7]));
+  const uint32_t span = hi - lo;
+  const int shift = span == 0 ? 0 : max(0, 32 - __clz(static_cast<int>(span)) - 12);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (t + 256 * r < cnt)
+      atomicAdd(&bucket[(static_cast<uint32_t>(key[r] >> 32) - lo) >> shift], 1);
+  }
+  __syncthreads();
+  int c[BPT], st[BPT];
+  int sum = 0, cmax = 0;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    c[k] = bucket[BPT * t + k];
+    sum += c[k];
+    cmax = max(cmax, c[k]);
+  }
+  if (__syncthreads_or(cmax > kSortBucketRun)) return false;
+  // exclusive scan of the per-thread bucket totals over the block
+  int incl = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) red[wave] = static_cast<uint32_t>(incl);
+  __syncthreads();
+  int run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += static_cast<int>(red[w]);
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    st[k] = run;
+    bucket[BPT * t + k] = run;
+    run += c[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (t + 256 * r < cnt) {
+      const int p = atomicAdd(&bucket[(static_cast<uint32_t>(key[r] >> 32) - lo) >> shift], 1);
+      out[p] = key[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    for (int i = st[k] + 1; i < st[k] + c[k]; ++i) {
+      const uint64_t v = out[i];
+      int p = i - 1;
+      while (p >= st[k] && out[p] > v) {
+        out[p + 1] = out[p];
+        --p;
+      }
+      out[p + 1] = v;
+    }
+  }
+  __syncthreads();
+  order_runs_and_store(a, list, cnt, out);
+  return true;
+}
+
 __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
   __shared__ uint64_t lds[256 * 16];
+  __shared__ int bucket[kSortBuckets];
+  __shared__ uint32_t red[8];
   const int64_t tile = blockIdx.x;
   const int cnt = min(a.cursor[tile], a.cap);
   if (cnt <= 1) return;
   uint64_t* list = a.lists + tile * a.cap;
   if (cnt <= 256) {
     sort_tile<1>(a, list, cnt, lds);
+  } else if (bucket_sort_tile(a, list, cnt, lds, bucket, red)) {
+    return;
   } else if (cnt <= 512) {
     sort_tile<2>(a, list, cnt, lds);
   } else if (cnt <= 1024) {

@@ -239,6 +239,37 @@ def test_depth_ties_and_float_equal_depths():
     _check(sc)
 
 
+def test_bucket_sort_tiles_with_float_equal_depths():
+    """Tiles of 257 to 4096 entries whose depths spread over many float values
+    take the bucket sort (no bucket overflows into the network); here a third
+    of the primitives repeat another one's z, so under the 1e-6 rad camera
+    tilt the lists hold exact ties and depths equal only once rounded to
+    float32, which must still composite in the oracle's (depth, index) order."""
+    rng = np.random.default_rng(22)
+    n = 3000
+    z = rng.uniform(3.0, 9.0, n)
+    z[: n // 3] = rng.choice(z[n // 3:], n // 3)
+    x = rng.uniform(-2.0, 2.0, n) * z / 4.0
+    y = rng.uniform(-1.5, 1.5, n) * z / 4.0
+    means = np.stack([x, y, z], -1).astype(np.float32)
+    th = 1e-6
+    R = np.array([[np.cos(th), 0.0, np.sin(th)], [0.0, 1.0, 0.0], [-np.sin(th), 0.0, np.cos(th)]])
+    cam = dict(R=R, t=np.zeros(3), fx=60.0, fy=60.0, cx=32.0, cy=24.0, width=64, height=48)
+    sc = W.SplatScene(means=means,
+                      scales=np.exp(rng.uniform(np.log(0.1), np.log(0.3), (n, 3))).astype(np.float32),
+                      rots=rng.standard_normal((n, 4)).astype(np.float32),
+                      opac=rng.uniform(0.05, 0.6, n).astype(np.float32),
+                      colors=rng.standard_normal((n, 3)).astype(np.float32),
+                      grad_image=rng.standard_normal((48, 64, 3)).astype(np.float32), cam=cam)
+    p = RR.project(sc.means, sc.scales, sc.rots, cam)
+    zf = p["z"][p["vis"]].astype(np.float32)
+    assert len(np.unique(zf)) < p["vis"].sum()                     # float-equal depths
+    tiles = np.bincount((p["v"][p["vis"]] // 16).astype(int).clip(0, 2) * 4 +
+                        (p["u"][p["vis"]] // 16).astype(int).clip(0, 3), minlength=12)
+    assert tiles.max() > 256                                       # tiles past the network's first size
+    _check(sc, cap=4096)
+
+
 def test_graph_replays_match_eager():
     """Both compositing calls allocate, copy and synchronise nothing: captured
     into a graph (with their output buffers), replays with eager work and
