@@ -57,7 +57,7 @@ namespace nasg {
 constexpr double kNear = 0.2;
 constexpr float kClamp = 0.99f;
 constexpr double kSupport = 9.0;
-constexpr int kBinParts = 8;  // tile classes of the binning pass, one per XCD
+constexpr int kBinParts = 8;  // most tile classes of the binning pass
 constexpr int kBinLdsTiles = 8192;      // class tiles one LDS-counting block holds
 constexpr int kBinPrimsPerThread = 32;  // primitives per thread of an LDS-counting block
 
@@ -276,55 +276,56 @@ __device__ inline uint64_t depth_key(double z, int64_t i) {
          static_cast<uint32_t>(i);
 }
 
-// Tile binning. Each of the chip's eight XCDs has its own L2 and workgroups
-// go to them in turn, so a list line filled from several XCDs reaches HBM as
-// several partial-line writes. The tiles are therefore split into eight
-// classes (tile index mod 8) and block b serves class b mod 8 for the
-// primitives of chunk b / 8: every list is written from one XCD, whose L2
-// merges its lines. The order of appends does not matter: the per-tile sort
-// orders each list by its keys.
+// Tile binning. A primitive's depth key goes to the list of every tile its
+// box touches; the order of appends does not matter (the per-tile sort orders
+// each list by its keys). The tiles are split into `parts` classes by tile
+// index mod parts (a power of two): block b serves class b mod parts for the
+// primitives of chunk b / parts.
 
-// Calls f(tile) for each tile of box r in class `part`: in each row, the
-// box's columns whose tile index is part mod kBinParts.
+// Calls f(tile) for each tile of box r in class `part` of `parts`: in each
+// row, the box's columns whose tile index is part mod parts.
 template <class F>
-__device__ inline void for_class_tiles(const BinRec& r, int64_t tiles_x, int part, F&& f) {
+__device__ inline void for_class_tiles(const BinRec& r, int64_t tiles_x, int part, int parts,
+                                       F&& f) {
   for (int y = r.ty0; y <= r.ty1; ++y) {
     const int64_t row = static_cast<int64_t>(y) * tiles_x;
-    for (int tx = r.tx0 + static_cast<int>((part - (row + r.tx0)) & (kBinParts - 1)); tx <= r.tx1;
-         tx += kBinParts)
+    for (int tx = r.tx0 + static_cast<int>((part - (row + r.tx0)) & (parts - 1)); tx <= r.tx1;
+         tx += parts)
       f(row + tx);
   }
 }
 
-// Images of up to kBinParts * kBinLdsTiles tiles. A block first counts its
+// Images whose tiles fit kBinLdsTiles per class in at most kBinParts classes
+// (parts = the smallest power of two that does it). A block first counts its
 // chunk's entries per class tile in LDS, then reserves each touched tile's
 // range in its list with one device atomic on the tile's cursor, then places
 // the keys in those ranges with LDS atomics: one device atomic per (block,
 // tile) instead of one per entry.
-__global__ __launch_bounds__(256) void raster_bin_lds(RasterArgs a) {
+__global__ __launch_bounds__(256) void raster_bin_lds(RasterArgs a, int pshift) {
   __shared__ int cnt[kBinLdsTiles];
-  const int part = static_cast<int>(blockIdx.x & (kBinParts - 1));
-  const int64_t first = static_cast<int64_t>(blockIdx.x / kBinParts) * (256 * kBinPrimsPerThread);
+  const int parts = 1 << pshift;
+  const int part = static_cast<int>(blockIdx.x & (parts - 1));
+  const int64_t first = static_cast<int64_t>(blockIdx.x >> pshift) * (256 * kBinPrimsPerThread);
   const int64_t last = min(first + 256 * kBinPrimsPerThread, a.n);
   const int64_t n_tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
-  const int n_local = static_cast<int>((n_tiles - part + kBinParts - 1) / kBinParts);
+  const int n_local = static_cast<int>((n_tiles - part + parts - 1) >> pshift);
   for (int m = threadIdx.x; m < n_local; m += 256) cnt[m] = 0;
   __syncthreads();
   for (int64_t i = first + threadIdx.x; i < last; i += 256) {
     const BinRec r = a.bins[i];
-    for_class_tiles(r, a.tiles_x, part, [&](int64_t t) { atomicAdd(&cnt[t / kBinParts], 1); });
+    for_class_tiles(r, a.tiles_x, part, parts, [&](int64_t t) { atomicAdd(&cnt[t >> pshift], 1); });
   }
   __syncthreads();
   for (int m = threadIdx.x; m < n_local; m += 256) {
     const int c = cnt[m];
-    if (c > 0) cnt[m] = atomicAdd(a.cursor + static_cast<int64_t>(m) * kBinParts + part, c);
+    if (c > 0) cnt[m] = atomicAdd(a.cursor + (static_cast<int64_t>(m) << pshift) + part, c);
   }
   __syncthreads();
   for (int64_t i = first + threadIdx.x; i < last; i += 256) {
     const BinRec r = a.bins[i];
     const uint64_t key = depth_key(r.z, i);
-    for_class_tiles(r, a.tiles_x, part, [&](int64_t t) {
-      const int pos = atomicAdd(&cnt[t / kBinParts], 1);
+    for_class_tiles(r, a.tiles_x, part, parts, [&](int64_t t) {
+      const int pos = atomicAdd(&cnt[t >> pshift], 1);
       if (pos < a.cap) {
         a.lists[t * a.cap + pos] = key;
       } else {
@@ -336,7 +337,9 @@ __global__ __launch_bounds__(256) void raster_bin_lds(RasterArgs a) {
 
 // Larger images: one device atomic per entry on the tile's cursor, those of
 // up to eight tiles issued before their results are used, so their latencies
-// overlap. Slot (row y, j) of a box is column first(y) + kBinParts * j, where
+// overlap. The tiles are split into kBinParts classes as above (each XCD of
+// the chip, which takes every eighth workgroup, then appends to its own
+// lists); slot (row y, j) of a box is column first(y) + kBinParts * j, where
 // first(y) is the box's first column in this class.
 __global__ void raster_bin(RasterArgs a) {
   const int part = static_cast<int>(blockIdx.x & (kBinParts - 1));
@@ -488,21 +491,16 @@ constexpr int kSortBucketRun = 32;
 
 __device__ bool bucket_sort_tile(const RasterArgs& a, uint64_t* list, int cnt, uint64_t* out,
                                  int* bucket, uint32_t* red) {
-  constexpr int R = 16;  // keys per thread at the most: 4096 = 256 x 16
-  constexpr int BPT = kSortBuckets / 256;
+  constexpr int BPT = kSortBuckets / 256;  // buckets owned by each thread
   const int t = static_cast<int>(threadIdx.x), lane = t & 63, wave = t >> 6;
-  uint64_t key[R];
+  // the keys' high words (float depth bits) are read from the list where
+  // only they are needed, which keeps the keys out of registers
+  const uint32_t* hw = reinterpret_cast<const uint32_t*>(list) + 1;
   uint32_t lo = 0xffffffffu, hi = 0u;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = t + 256 * r;
-    key[r] = 0;
-    if (e < cnt) {
-      key[r] = list[e];
-      const uint32_t h = static_cast<uint32_t>(key[r] >> 32);
-      lo = min(lo, h);
-      hi = max(hi, h);
-    }
+  for (int e = t; e < cnt; e += 256) {
+    const uint32_t h = hw[2 * e];
+    lo = min(lo, h);
+    hi = max(hi, h);
   }
   for (int k = t; k < kSortBuckets; k += 256) bucket[k] = 0;
   for (int o = 32; o >= 1; o >>= 1) {
@@ -518,13 +516,9 @@ __device__ bool bucket_sort_tile(const RasterArgs& a, uint64_t* list, int cnt, u
   hi = max(max(red[4], red[5]), max(red[6], red[7]));
   const uint32_t span = hi - lo;
   const int shift = span == 0 ? 0 : max(0, 32 - __clz(static_cast<int>(span)) - 12);
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (t + 256 * r < cnt)
-      atomicAdd(&bucket[(static_cast<uint32_t>(key[r] >> 32) - lo) >> shift], 1);
-  }
+  for (int e = t; e < cnt; e += 256) atomicAdd(&bucket[(hw[2 * e] - lo) >> shift], 1);
   __syncthreads();
-  int c[BPT], st[BPT];
+  int c[BPT];
   int sum = 0, cmax = 0;
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
@@ -545,25 +539,23 @@ __device__ bool bucket_sort_tile(const RasterArgs& a, uint64_t* list, int cnt, u
   for (int w = 0; w < wave; ++w) run += static_cast<int>(red[w]);
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
-    st[k] = run;
     bucket[BPT * t + k] = run;
     run += c[k];
   }
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (t + 256 * r < cnt) {
-      const int p = atomicAdd(&bucket[(static_cast<uint32_t>(key[r] >> 32) - lo) >> shift], 1);
-      out[p] = key[r];
-    }
+  for (int e = t; e < cnt; e += 256) {
+    const uint64_t key = list[e];
+    out[atomicAdd(&bucket[(static_cast<uint32_t>(key >> 32) - lo) >> shift], 1)] = key;
   }
   __syncthreads();
-#pragma unroll
+  // bucket b now ends at bucket[b] and starts where bucket b - 1 ends
   for (int k = 0; k < BPT; ++k) {
-    for (int i = st[k] + 1; i < st[k] + c[k]; ++i) {
+    const int b = BPT * t + k;
+    const int s0 = b == 0 ? 0 : bucket[b - 1], s1 = bucket[b];
+    for (int i = s0 + 1; i < s1; ++i) {
       const uint64_t v = out[i];
       int p = i - 1;
-      while (p >= st[k] && out[p] > v) {
+      while (p >= s0 && out[p] > v) {
         out[p + 1] = out[p];
         --p;
       }
@@ -585,9 +577,24 @@ __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
   uint64_t* list = a.lists + tile * a.cap;
   if (cnt <= 256) {
     sort_tile<1>(a, list, cnt, lds);
-  } else if (bucket_sort_tile(a, list, cnt, lds, bucket, red)) {
-    return;
-  } else if (cnt <= 512) {
+  } else if (!bucket_sort_tile(a, list, cnt, lds, bucket, red)) {
+    // left to raster_sort_network, which this mark (the tile's count, bit
+    // inverted) tells to take the tile and restore the count; every thread
+    // read the cursor before the barrier inside the bucket sort
+    if (threadIdx.x == 0) a.cursor[tile] = ~a.cursor[tile];
+  }
+}
+
+// The tiles the bucket sort left: the bitonic network, whose registers would
+// otherwise cap the occupancy of every tile's sort.
+__global__ __launch_bounds__(256) void raster_sort_network(RasterArgs a) {
+  __shared__ uint64_t lds[256 * 16];
+  const int64_t tile = blockIdx.x;
+  const int c = a.cursor[tile];
+  if (c >= 0) return;
+  const int cnt = min(~c, a.cap);
+  uint64_t* list = a.lists + tile * a.cap;
+  if (cnt <= 512) {
     sort_tile<2>(a, list, cnt, lds);
   } else if (cnt <= 1024) {
     sort_tile<4>(a, list, cnt, lds);
@@ -596,6 +603,8 @@ __global__ __launch_bounds__(256) void raster_sort(RasterArgs a) {
   } else {
     sort_tile<16>(a, list, cnt, lds);
   }
+  __syncthreads();  // every thread has read the mark
+  if (threadIdx.x == 0) a.cursor[tile] = ~c;
 }
 
 struct StageEntry {
@@ -1018,15 +1027,19 @@ hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
     hipLaunchKernelGGL(raster_begin, dim3(gt), dim3(256), 0, s, a);
     if (a.n > 0) {
       hipLaunchKernelGGL(raster_project, dim3(gn), dim3(256), 0, s, a);
-      if ((n_tiles + kBinParts - 1) / kBinParts <= kBinLdsTiles) {
+      int pshift = 0;  // 2^pshift tile classes, the fewest that fit the LDS counters
+      while ((1 << pshift) < kBinParts && ((n_tiles - 1) >> pshift) + 1 > kBinLdsTiles) ++pshift;
+      if (((n_tiles - 1) >> pshift) + 1 <= kBinLdsTiles) {
         const int64_t chunk = 256 * kBinPrimsPerThread;
         const unsigned gc = static_cast<unsigned>((a.n + chunk - 1) / chunk);
-        hipLaunchKernelGGL(raster_bin_lds, dim3(gc * kBinParts), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(raster_bin_lds, dim3(gc << pshift), dim3(256), 0, s, a, pshift);
       } else {
         hipLaunchKernelGGL(raster_bin, dim3(gn * kBinParts), dim3(256), 0, s, a);
       }
     }
     hipLaunchKernelGGL(raster_sort, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(raster_sort_network, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
+                       a);
     hipLaunchKernelGGL(raster_render_fwd<kFwdRows>, dim3(static_cast<unsigned>(n_tiles)),
                        dim3(256 / kFwdRows), 0, s, a);
   } else {
