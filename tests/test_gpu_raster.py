@@ -81,6 +81,22 @@ def test_opacities_at_the_clamp():
     _check(sc)
 
 
+def test_zero_and_tiny_opacities():
+    """A fifth of the primitives have opacity 0 and a fifth 1e-30 (alpha is
+    zero or far below every other layer): they add nothing to the image, yet
+    their opacity gradient, T rho times dL/dalpha summed over their pixels, is
+    of the usual size and must match the oracle, as must everything behind
+    and in front of them."""
+    sc = W.draw_splat_scene(4, 400, 48, 40, scale=(0.05, 0.4))
+    rng = np.random.default_rng(40)
+    k = rng.permutation(sc.n)
+    sc.opac[k[: sc.n // 5]] = 0.0
+    sc.opac[k[sc.n // 5: 2 * sc.n // 5]] = 1e-30
+    img, ref = _check(sc)
+    gc, go = _gpu(sc)[1:3]
+    assert np.abs(go[k[: 2 * sc.n // 5]]).max() > 1e-3    # nonzero at alpha = 0
+
+
 def test_nothing_visible():
     """All primitives behind the near plane: black image, zero gradients."""
     sc = W.draw_splat_scene(4, 64, 40, 30, scale=(0.1, 0.4), behind=1.0)
