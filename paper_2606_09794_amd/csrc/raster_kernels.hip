@@ -16,13 +16,15 @@
 //   project : per primitive, FP64 pixel mean, inverse 2D covariance, depth and
 //             the 16 x 16-pixel tiles its ellipse's bounding box touches, kept
 //             with the colour and opacity in a 64-byte render record;
-//   bin     : each primitive appends its 64-bit depth key (float depth bits,
-//             index) to the lists of those tiles (an atomic cursor per tile,
-//             fixed capacity per tile; entries beyond it are dropped and
-//             flagged);
-//   sort    : per tile, the list is sorted by (depth, primitive index) with
-//             a bitonic network on 64-bit keys held in registers and LDS,
-//             which fixes the compositing order;
+//   bin     : each primitive's 64-bit depth key (float depth bits, index)
+//             goes to the lists of those tiles (a cursor per tile, fixed
+//             capacity per tile; entries beyond it are dropped and flagged);
+//             blocks count their entries per tile in LDS and take one device
+//             atomic per touched tile;
+//   sort    : per tile, the list is sorted by (depth, primitive index), which
+//             fixes the compositing order: a bucket sort on the depth bits in
+//             LDS, or a bitonic network on the 64-bit keys for small tiles
+//             and for tiles whose depths crowd into few buckets;
 //   render  : one block per tile, each lane one or more pixels of one column
 //             (they share the entry's dx terms), front to back over the list
 //             in chunks staged through LDS; an entry's q <= 9 box decides per
@@ -38,8 +40,9 @@
 //             convex-combination recursion (no cancellation at any depth),
 //             and T_i recovered from the forward's final transmittance. Per
 //             primitive, a lane sums its pixels' terms, the wavefront
-//             sums over lanes in registers, and one lane adds the sums to
-//             FP64 per-primitive accumulators with one atomic per value. With
+//             totals them over its lanes by halving exchanges, and the lanes
+//             holding the totals add them to FP64 per-primitive accumulators
+//             with one atomic instruction. With
 //             geometry gradients the same pass also sums dL/d(u, v, a, b, c)
 //             (dL/dq = -sigma rho / 2 times the pixel's dL/dalpha);
 //   finish  : per primitive, the accumulators rounded to the float32
