@@ -235,12 +235,57 @@ def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
     return out
 
 
+def profile_other(args, log):
+    """Counter-collection mode of the single-camera, bf16 K=16 and uneven-batch
+    workloads: only the launch their bench line times (the persistent batch
+    with --tile-iters / --blocks-per-cu), --steps times."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    if args.workload in ("single-camera", "bf16-k16"):
+        w = W.config1(n=args.n) if args.workload == "single-camera" else W.config3(n=args.n)
+        d = upload(w)
+        g = P.nasg_grad_buffers(w.k, w.n, "cuda")
+        rgb = torch.empty((w.v, w.n, 3), device="cuda")
+        for _ in range(args.steps):
+            P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"], means=d["means"],
+                            cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
+        lb = LOBE_BYTES_BF16 if args.workload == "bf16-k16" else LOBE_BYTES_F32
+        info = {"n": w.n, "k": w.k, "v": w.v, "evals": w.n * w.v,
+                "algorithmic_bytes_per_launch": algorithmic_bytes(w.n, w.k, w.v, lobe_bytes=lb)}
+    elif args.workload == "uneven-batch":
+        scenes = W.config4()
+        dev = []
+        for sc in scenes:
+            dd = upload(sc.workload)
+            dd["grads"] = P.nasg_grad_buffers(sc.workload.k, sc.workload.n, "cuda")
+            dd["rgb"] = torch.empty((sc.workload.v, sc.workload.n, 3), device="cuda")
+            dev.append(dd)
+        plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=args.tile_iters,
+                               blocks_per_cu=args.blocks_per_cu)
+        for _ in range(args.steps):
+            plan.run()
+        info = {"scenes": len(scenes), "evals": sum(s.workload.n * s.workload.v for s in scenes),
+                "tile_iters": args.tile_iters, "blocks_per_cu": args.blocks_per_cu,
+                "algorithmic_bytes_per_launch": sum(algorithmic_bytes(s.workload.n, s.workload.k,
+                                                                      s.workload.v) for s in scenes)}
+    else:
+        raise SystemExit("--profile: headline, single-camera, bf16-k16 or uneven-batch")
+    torch.cuda.synchronize()
+    print(json.dumps(dict(profile=True, workload=args.workload, launches=args.steps,
+                          source_hash=kernel_source_hash(), **info)), flush=True)
+
+
 def bench_other(args, log):
     """Workloads other than the headline: single camera, bf16 K=16, uneven batch."""
     import torch
 
     import paper_2606_09794_amd as P
     import workloads as W
+    if args.profile:
+        profile_other(args, log)
+        return
     res = {"metric": METRIC, "unit": "G evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic"}
@@ -587,8 +632,14 @@ def main():
                          "calibration) or the degree-3 SH fused launch on the same inputs")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a few headline launches plus a plain "
-                         "device copy of --copy-mib MiB for calibrating byte counters")
+                         "device copy of --copy-mib MiB for calibrating byte counters; with "
+                         "--workload single-camera, bf16-k16 or uneven-batch, that workload's "
+                         "timed launch only")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--tile-iters", type=int, default=8,
+                    help="with --profile --workload uneven-batch: tile passes per work item")
+    ap.add_argument("--blocks-per-cu", type=int, default=4,
+                    help="with --profile --workload uneven-batch: persistent blocks per CU")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params",
                              "families", "training-view"],
