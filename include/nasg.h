@@ -257,6 +257,10 @@ typedef struct nasg_batch { /* filled by nasg_batched_plan                    */
   int32_t grid;           /* persistent blocks launched by nasg_batched_run   */
   int32_t norm;
   uint64_t token;         /* identifies the plan written to the workspace     */
+  int32_t raw;            /* 1 if a scene has the paper's raw values: the run
+                             then launches the kernel that carries their lane
+                             mappings too (more registers spilled)            */
+  int32_t pad;
 } nasg_batch;
 
 /* Device bytes needed for the plan of these scenes (host-side computation;

@@ -48,7 +48,7 @@ class NasgBatchTuning(C.Structure):
 class NasgBatch(C.Structure):
     _fields_ = [("workspace", C.c_void_p), ("bytes", C.c_size_t), ("n_items", C.c_int32),
                 ("n_scenes", C.c_int32), ("grid", C.c_int32), ("norm", C.c_int32),
-                ("token", C.c_uint64)]
+                ("token", C.c_uint64), ("raw", C.c_int32), ("pad", C.c_int32)]
 
 
 class NasgTuning(C.Structure):

@@ -450,12 +450,17 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
   out->grid = std::max(1, cus * tt.blocks_per_cu);
   out->norm = norm;
   out->token = token;
+  out->raw = 0;
+  for (int32_t s = 0; s < n_scenes; ++s)
+    if (bs[s].variant >= 3) out->raw = 1;
+  out->pad = 0;
   return NASG_OK;
 }
 
 int nasg_batched_run(const nasg_batch* b, void* stream) {
   if (b == nullptr || b->workspace == nullptr) return NASG_ERR_NULL;
-  if (b->n_scenes < 0 || b->n_items < 0 || b->grid < 1) return NASG_ERR_WORKSPACE;
+  if (b->n_scenes < 0 || b->n_items < 0 || b->grid < 1 || (b->raw != 0 && b->raw != 1))
+    return NASG_ERR_WORKSPACE;
   if (b->n_items == 0) return NASG_OK;
   auto* base = static_cast<unsigned char*>(b->workspace);
   auto* hdr = reinterpret_cast<nasg::BatchHeader*>(base);
@@ -464,7 +469,7 @@ int nasg_batched_run(const nasg_batch* b, void* stream) {
       align_up(sizeof(nasg::BatchHeader) + sizeof(nasg::BatchScene) * b->n_scenes, 64);
   auto* items = reinterpret_cast<const nasg::BatchItem*>(base + items_off);
   const hipError_t e = nasg::launch_batched(hdr, scenes, items, &hdr->counter, b->token, b->grid,
-                                            static_cast<hipStream_t>(stream));
+                                            b->raw != 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
 }
 

@@ -318,8 +318,12 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 
 // Pulls tiles from the queue until it is empty; every block exits when the
 // head passes n_items. A plan whose token does not match is not run.
-// Two waves per SIMD: the three inlined lane mappings would otherwise need
-// more registers than that occupancy allows.
+// Two waves per SIMD: the inlined lane mappings would otherwise need more
+// registers than that occupancy allows. RAW: the plan has scenes with the
+// paper's raw values, so all six mappings are inlined; without them only the
+// three quaternion mappings are (4 VGPRs spilled instead of 44), and an item
+// of a raw-value scene, which such a plan never holds, is skipped.
+template <bool RAW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void nasg_batched_kernel(const BatchHeader* hdr,
                                                            const BatchScene* scenes,
@@ -338,24 +342,38 @@ void nasg_batched_kernel(const BatchHeader* hdr,
     if (it >= n_items) break;
     const BatchItem item = load_uniform(items + it);
     const BatchScene sc = load_uniform(scenes + item.scene);
-    switch (sc.variant) {
-      case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-      case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-      case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-      case 3: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-      case 4: batch_tile<2, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-      default: batch_tile<8, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+    if constexpr (RAW) {
+      switch (sc.variant) {
+        case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 3: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 4: batch_tile<2, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+        default: batch_tile<8, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+      }
+    } else {
+      switch (sc.variant) {
+        case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        default: break;
+      }
     }
   }
 }
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
-                          uint32_t* counter, uint64_t token, int grid, hipStream_t s) {
+                          uint32_t* counter, uint64_t token, int grid, bool raw, hipStream_t s) {
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(nasg_batched_kernel, dim3(grid), dim3(256), 0, s, hdr, scenes, items, counter,
-                     token);
+  if (raw) {
+    hipLaunchKernelGGL(nasg_batched_kernel<true>, dim3(grid), dim3(256), 0, s, hdr, scenes, items,
+                       counter, token);
+  } else {
+    hipLaunchKernelGGL(nasg_batched_kernel<false>, dim3(grid), dim3(256), 0, s, hdr, scenes, items,
+                       counter, token);
+  }
   return hipGetLastError();
 }
 

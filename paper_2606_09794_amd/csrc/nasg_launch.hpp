@@ -106,7 +106,7 @@ struct BatchItem {
 constexpr int kBatchLanes[6] = {1, 2, 8, 1, 2, 8};
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
-                          uint32_t* counter, uint64_t token, int grid, hipStream_t s);
+                          uint32_t* counter, uint64_t token, int grid, bool raw, hipStream_t s);
 
 // SG, SB, SC and ASG lobes (csrc/family_kernels.hip), lane mapping by view count.
 hipError_t launch_family(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s);
