@@ -150,6 +150,9 @@ def test_batched_rejects(lib):
     assert lib.nasg_batched_run(None, None) == -1
     empty = L.NasgBatch(FAKE, 0, 0, 0, 1, 0, 0)
     assert lib.nasg_batched_run(C.byref(empty), None) == 0      # nothing to launch
+    bad = L.NasgBatch(FAKE, 0, 5, 1, 1, 0, 1, 2)                # raw-values flag neither 0 nor 1
+    assert lib.nasg_batched_run(C.byref(bad), None) == -7
+    assert C.sizeof(L.NasgBatch) == 48                          # the C layout of nasg_batch
     # the work list grows with the tile count: at V = 2 a primitive has 2 lanes, so
     # one tile is 4 passes x 128 primitives
     sc[0].grad_rgb = FAKE
