@@ -349,6 +349,31 @@ def test_widest_image_on_windows():
             compare(v[idx], ref[name], scale[name], f"grad {name} x0={x0}", TOL)
 
 
+@pytest.mark.parametrize("width,height,classes", [(2560, 1440, 2), (3840, 2160, 4), (5120, 2880, 8)])
+def test_binning_tile_classes_on_windows(width, height, classes):
+    """Images of 14 400, 32 400 and 57 600 tiles: binning splits the tiles
+    into 2, 4 and 8 classes so that each fits the LDS counters (8192 tiles
+    per class). 300 000 primitives; two windows, one at the far corner,
+    against the oracle."""
+    tiles = ((width + 15) // 16) * ((height + 15) // 16)
+    assert (tiles - 1) // classes + 1 <= 8192 < (tiles - 1) // (classes // 2) + 1
+    sc = W.draw_splat_scene(34 + classes, 300_000, width, height, scale=(1e-3, 1e-2))
+    img, gc, go = _gpu(sc, cap=1024)
+    for x0, y0 in ((width // 3, height // 2), (width - 48, height - 32)):
+        w, h = 48, 32
+        g = np.zeros_like(sc.grad_image)
+        g[y0:y0 + h, x0:x0 + w] = sc.grad_image[y0:y0 + h, x0:x0 + w]
+        img_w, gc_w, go_w, gm_w, gs_w, gr_w = _gpu(sc, cap=1024, grad_image=g, geometry=True)
+        idx, ref, scale = _window_oracle(sc, x0, y0, w, h)
+        assert len(idx) > 20
+        at = f"{width}x{height} x0={x0} y0={y0}"
+        compare(img[y0:y0 + h, x0:x0 + w], ref["image"], scale["image"], f"image window {at}", TOL)
+        compare(gc_w[idx], ref["colors"], scale["colors"], f"grad colors {at}", TOL)
+        compare(go_w[idx], ref["opac"], scale["opac"], f"grad opac {at}", TOL)
+        for name, v in zip(GEOM, (gm_w, gs_w, gr_w)):
+            compare(v[idx], ref[name], scale[name], f"grad {name} {at}", TOL)
+
+
 def test_many_tiles_on_windows():
     """An 8192 x 4352 image (512 x 272 = 139 264 tiles, more than the binning
     pass counts per tile class in LDS, so it takes the per-entry path) with
