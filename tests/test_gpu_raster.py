@@ -286,6 +286,28 @@ def test_bucket_sort_tiles_with_float_equal_depths():
     _check(sc, cap=4096)
 
 
+@pytest.mark.parametrize("n", [1500, 3000])
+def test_network_sort_for_crowded_depths(n):
+    """Every primitive at exactly the same depth in a 32 x 32 image (four
+    tiles, each reached by nearly all of them): the bucket sort cannot split
+    the depths and leaves the tiles to the bitonic network, here with
+    1025-2048 and 2049-4096 keys (8 and 16 keys per thread); equal depths
+    composite in index order, as in the oracle."""
+    rng = np.random.default_rng(50 + n)
+    means = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), np.full(n, 4.0)],
+                     -1).astype(np.float32)
+    cam = dict(R=np.eye(3), t=np.zeros(3), fx=40.0, fy=40.0, cx=16.0, cy=16.0, width=32, height=32)
+    sc = W.SplatScene(means=means,
+                      scales=np.exp(rng.uniform(np.log(0.3), np.log(0.6), (n, 3))).astype(np.float32),
+                      rots=rng.standard_normal((n, 4)).astype(np.float32),
+                      opac=rng.uniform(0.01, 0.05, n).astype(np.float32),
+                      colors=rng.standard_normal((n, 3)).astype(np.float32),
+                      grad_image=rng.standard_normal((32, 32, 3)).astype(np.float32), cam=cam)
+    p = RR.project(sc.means, sc.scales, sc.rots, cam)
+    assert p["vis"].all() and len(np.unique(p["z"])) == 1
+    _check(sc, cap=4096)
+
+
 def test_graph_replays_match_eager():
     """Both compositing calls allocate, copy and synchronise nothing: captured
     into a graph (with their output buffers), replays with eager work and
