@@ -105,6 +105,28 @@ def measured_counters(key, files=APPEARANCE_SOURCES):
     return ent
 
 
+def counters_roofline(key, ms, ab, evals, alu):
+    """Roofline object of a launch from the committed counters for `key`: the
+    calibrated HBM bytes as its traffic and, with `alu`, the VALU
+    lane-instruction rate against the issue peak as the bound with the HBM
+    figures beside it. Missing counters, or counters taken on other kernel
+    sources, give the HBM roofline with unknown traffic."""
+    hbm = {"achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": ab}
+    c = measured_counters(key)
+    if c is None:
+        return dict(hbm, bound="hbm", traffic=None)
+    extra = {"profiled_launch": c["profiled_launch"]} if "profiled_launch" in c else {}
+    if not alu:
+        return dict(hbm, bound="hbm", traffic=c["bytes_per_launch"], **extra)
+    lane = c["valu_wave_instructions_per_launch"] * 64
+    ach = lane / (ms * 1e-3) / 1e12
+    return dict({"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                 "unit": "T VALU lane-instructions/s", "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
+                 "traffic": c["bytes_per_launch"], "lane_instructions_per_eval": round(lane / evals, 1),
+                 "hbm": hbm}, **extra)
+
+
 # ----------------------------------------------------------------- CPU oracle
 
 _CPU_W = None   # workload shared with forked oracle workers
@@ -307,9 +329,8 @@ def bench_other(args, log):
         res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
                    config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x 1 camera, FP32, "
                                        f"{args.norm} normaliser", "primitives": n, "lobes": k, "views": v},
-                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
-                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", ms, ab, n * v,
+                                              alu=False),
                    compare={"sh3_fused": {"ms": round(msh, 4), "G_evals_s": round(n * v / msh / 1e6, 4),
                                           "hbm_frac": round(sh_bytes(n, v) / msh / 1e6 / HBM_PEAK_GBS, 4)},
                             "hbm_copy_ceiling": copy_ceiling(args.steps)},
@@ -340,9 +361,8 @@ def bench_other(args, log):
                    config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
                                        f"lobe parameters stored in bf16, {args.norm} normaliser",
                            "primitives": n, "lobes": k, "views": v},
-                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
-                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}_bf16", ms, ab,
+                                              n * v, alu=True),
                    compare={"fp32_storage_same_values": {"ms": round(ms32, 4),
                                                          "G_evals_s": round(n * v / ms32 / 1e6, 4),
                                                          "algorithmic_bytes_per_launch": ab32}},
@@ -465,9 +485,8 @@ def bench_other(args, log):
                                        f"{args.norm} normaliser", "scenes": len(scenes),
                            "primitives": sum(s.workload.n for s in scenes), "evals": evals,
                            "tile_iters": ti, "blocks_per_cu": bpc, "work_items": plan.n_items},
-                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
-                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   roofline=counters_roofline(f"nasg_batch_uneven{len(scenes)}_{args.norm}", ms, ab,
+                                              evals, alu=True),
                    compare={"graph_replay": {"ms": round(ms_graph, 4),
                                              "G_evals_s": round(evals / ms_graph / 1e6, 4)},
                             "per_scene_launches": {"ms": round(ms_sep, 4),

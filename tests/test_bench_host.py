@@ -66,6 +66,24 @@ def test_committed_counters_match_their_sources():
     assert bench.measured_counters("nasg_fused_k8_v16_n3000000_exact") is not None
     assert bench.measured_counters("raster_render_bwd_geom_n3000000_1920x1080",
                                    bench.RASTER_SOURCES) is not None
+    for key in ("nasg_fused_k8_v1_n1048576_exact", "nasg_fused_k16_v8_n6000000_exact_bf16",
+                "nasg_batch_uneven32_exact"):
+        assert bench.measured_counters(key) is not None, key
+
+
+def test_counters_roofline_bounds():
+    """The single-camera line stays on the HBM roof with its measured traffic;
+    the VALU-bound lines (bf16 K = 16, the persistent batch) report the issue
+    rate with the HBM figures beside; unknown counters give the HBM roof with
+    unknown traffic."""
+    ab = bench.algorithmic_bytes(1 << 20, 8, 1)
+    r = bench.counters_roofline("nasg_fused_k8_v1_n1048576_exact", 0.25, ab, 1 << 20, alu=False)
+    assert r["bound"] == "hbm" and r["traffic"] > ab and r["achieved"] == round(ab / 0.25 / 1e6, 1)
+    r = bench.counters_roofline("nasg_batch_uneven32_exact", 13.0, 25_156_165_456, 171_865_438, alu=True)
+    assert r["bound"] == "alu" and 0 < r["frac"] < 1 and r["hbm"]["algorithmic_bytes_per_launch"] > 0
+    assert r["profiled_launch"] == {"tile_iters": 8, "blocks_per_cu": 4}
+    r = bench.counters_roofline("no_such_key", 1.0, 1000, 10, alu=True)
+    assert r["bound"] == "hbm" and r["traffic"] is None
 
 
 @pytest.mark.parametrize("n", [2, 8])
