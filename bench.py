@@ -258,21 +258,27 @@ def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
 
 
 def profile_other(args, log):
-    """Counter-collection mode of the single-camera, bf16 K=16 and uneven-batch
-    workloads: only the launch their bench line times (the persistent batch
-    with --tile-iters / --blocks-per-cu), --steps times."""
+    """Counter-collection mode of the single-camera, bf16 K=16, paper-params and
+    uneven-batch workloads: only the launch their bench line times (the
+    persistent batch with --tile-iters / --blocks-per-cu), --steps times."""
     import torch
 
     import paper_2606_09794_amd as P
     import workloads as W
-    if args.workload in ("single-camera", "bf16-k16"):
-        w = W.config1(n=args.n) if args.workload == "single-camera" else W.config3(n=args.n)
+    if args.workload in ("single-camera", "bf16-k16", "paper-params"):
+        param = "angles" if args.workload == "paper-params" else "quat"
+        if args.workload == "single-camera":
+            w = W.config1(n=args.n)
+        elif args.workload == "bf16-k16":
+            w = W.config3(n=args.n)
+        else:
+            w = W.draw_workload(7, args.n, 8, args.views, with_sh=False, param="angles")
         d = upload(w)
         g = P.nasg_grad_buffers(w.k, w.n, "cuda")
         rgb = torch.empty((w.v, w.n, 3), device="cuda")
         for _ in range(args.steps):
             P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"], means=d["means"],
-                            cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
+                            cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb, param=param)
         lb = LOBE_BYTES_BF16 if args.workload == "bf16-k16" else LOBE_BYTES_F32
         info = {"n": w.n, "k": w.k, "v": w.v, "evals": w.n * w.v,
                 "algorithmic_bytes_per_launch": algorithmic_bytes(w.n, w.k, w.v, lobe_bytes=lb)}
@@ -293,7 +299,7 @@ def profile_other(args, log):
                 "algorithmic_bytes_per_launch": sum(algorithmic_bytes(s.workload.n, s.workload.k,
                                                                       s.workload.v) for s in scenes)}
     else:
-        raise SystemExit("--profile: headline, single-camera, bf16-k16 or uneven-batch")
+        raise SystemExit("--profile: headline, single-camera, bf16-k16, paper-params or uneven-batch")
     torch.cuda.synchronize()
     print(json.dumps(dict(profile=True, workload=args.workload, launches=args.steps,
                           source_hash=kernel_source_hash(), **info)), flush=True)
@@ -393,9 +399,8 @@ def bench_other(args, log):
                                        f"the paper's raw lobe values (three frame cosines and "
                                        f"activations), FP32, {args.norm} normaliser",
                            "primitives": n, "lobes": k, "views": v, "param": "angles"},
-                   roofline={"bound": "hbm", "achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
-                             "traffic": None, "algorithmic_bytes_per_launch": ab},
+                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}_angles", ms, ab,
+                                              n * v, alu=True),
                    compare={"quaternion_parametrisation_same_sizes": {
                        "ms": round(msq, 4), "G_evals_s": round(n * v / msq / 1e6, 4)}},
                    parity_sampled_max_scaled_error=par)
@@ -652,8 +657,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a few headline launches plus a plain "
                          "device copy of --copy-mib MiB for calibrating byte counters; with "
-                         "--workload single-camera, bf16-k16 or uneven-batch, that workload's "
-                         "timed launch only")
+                         "--workload single-camera, bf16-k16, paper-params or uneven-batch, "
+                         "that workload's timed launch only")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--tile-iters", type=int, default=8,
                     help="with --profile --workload uneven-batch: tile passes per work item")

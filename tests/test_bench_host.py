@@ -67,7 +67,7 @@ def test_committed_counters_match_their_sources():
     assert bench.measured_counters("raster_render_bwd_geom_n3000000_1920x1080",
                                    bench.RASTER_SOURCES) is not None
     for key in ("nasg_fused_k8_v1_n1048576_exact", "nasg_fused_k16_v8_n6000000_exact_bf16",
-                "nasg_batch_uneven32_exact"):
+                "nasg_fused_k8_v16_n3000000_exact_angles", "nasg_batch_uneven32_exact"):
         assert bench.measured_counters(key) is not None, key
 
 
