@@ -431,10 +431,9 @@ def bench_other(args, log):
                    config={"workload": f"lobe families of the distribution table, K={k} fused fwd+bwd, "
                                        f"{n} primitives x {v} cameras each, FP32; value = NASGabor",
                            "primitives": n, "lobes": k, "views": v},
-                   roofline={"bound": "hbm", "achieved": round(ab / best["ms"] / 1e6, 1),
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(ab / best["ms"] / 1e6 / HBM_PEAK_GBS, 4), "traffic": None,
-                             "algorithmic_bytes_per_launch": ab},
+                   # the NASGabor launch is the headline's kernel at the headline's sizes
+                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", best["ms"], ab,
+                                              n * v, alu=True),
                    families=per)
     elif args.workload == "uneven-batch":
         t0 = time.perf_counter()
