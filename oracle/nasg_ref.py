@@ -58,11 +58,14 @@ def frame_from_quat(q):
     the workloads parametrise it by a quaternion instead of three cosines.
     """
     q = np.asarray(q, dtype=np.float64)
-    qn = q / np.linalg.norm(q, axis=-1, keepdims=True)
-    w, x, y, z = qn[..., 0], qn[..., 1], qn[..., 2], qn[..., 3]
-    ax = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)], -1)
-    ay = np.stack([2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)], -1)
-    az = np.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)], -1)
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    ww, xx, yy, zz = w * w, x * x, y * y, z * z
+    n2 = (ww + xx + yy + zz)[..., None]
+    # R(q/|q|) = M(q)/|q|^2 with M homogeneous of degree 2 in q (one rounding
+    # of |q|^2 instead of one per normalised component)
+    ax = np.stack([ww + xx - yy - zz, 2 * (x * y + w * z), 2 * (x * z - w * y)], -1) / n2
+    ay = np.stack([2 * (x * y - w * z), ww - xx + yy - zz, 2 * (y * z + w * x)], -1) / n2
+    az = np.stack([2 * (x * z + w * y), 2 * (y * z - w * x), ww - xx - yy + zz], -1) / n2
     return ax, ay, az
 
 
@@ -193,9 +196,25 @@ def exp_sinhc(lam_big, k):
 
 
 def psi(lam_big, k):
-    """Psi(Lam, k) of Section 5.1 with its partials (Psi, dPsi/dLam, dPsi/dk)."""
-    L = np.asarray(lam_big, np.float64)
-    k = np.asarray(k, np.float64)
+    """Psi(Lam, k) of Section 5.1 with its partials and 1 - Psi:
+    (Psi, dPsi/dLam, dPsi/dk, 1 - Psi).
+
+    Where Lam^2 - k^2 > 1, s = sqrt(Lam^2 - k^2) and delta = Lam - s =
+    k^2 / (Lam + s), and Psi = (Lam/s) e^{-delta} (1 - e^{-2s}) / (1 - e^{-2Lam})
+    is the same expression regrouped; its log-derivatives
+        d ln Psi/dLam = (1/Lam - Lam/s^2) + delta/s
+                        + 2 [(Lam/s) g(s) - g(Lam)],   g(x) = 1/(e^{2x} - 1),
+        d ln Psi/dk   = (k/s) (1/s - 1 - 2 g(s)),
+    are written with 1/Lam - Lam/s^2 = -k^2/(Lam s^2), Lam/s - 1 = delta/s and
+    g(s) - g(Lam) = expm1(2 delta) e^{-2Lam} / ((1 - e^{-2s})(1 - e^{-2Lam})),
+    so that every term vanishes with k instead of cancelling (Psi = 1 at
+    k = 0), and ln Psi = -log1p(-delta/Lam) - delta
+    + log1p(e^{-2s} expm1(-2 delta) / (1 - e^{-2Lam})) gives 1 - Psi with
+    relative accuracy. Elsewhere the partials come from differentiating
+    e^{-Lam} sinhc directly."""
+    L, k = np.broadcast_arrays(np.asarray(lam_big, np.float64), np.asarray(k, np.float64))
+    shp = L.shape
+    L, k = L.reshape(-1), k.reshape(-1)
     F, dFs = exp_sinhc(L, k)
     D = -np.expm1(-2 * L)                    # 1 - e^{-2 Lam}
     dF_dL = -F + dFs * 2 * L
@@ -203,7 +222,24 @@ def psi(lam_big, k):
     P = 2 * L * F / D
     dP_dL = 2 * F / D + 2 * L * dF_dL / D - 2 * L * F * (2 * np.exp(-2 * L)) / D ** 2
     dP_dk = 2 * L * dF_dk / D
-    return P, dP_dL, dP_dk
+    omP = 1 - P
+    hyp = L * L - k * k > 1.0
+    if np.any(hyp):
+        Lh, kh, Dh = L[hyp], k[hyp], D[hyp]
+        s = np.sqrt(Lh * Lh - kh * kh)
+        delta = kh * kh / (Lh + s)
+        Ds = -np.expm1(-2 * s)               # 1 - e^{-2s}
+        gs = np.exp(-2 * s) / Ds
+        dlnL = (-kh * kh / (Lh * s * s) + delta / s * (1 + 2 * gs)
+                + 2 * np.expm1(2 * delta) * np.exp(-2 * Lh) / (Ds * Dh))
+        dlnk = kh / s * (1 / s - 1 - 2 * gs)
+        lnP = (-np.log1p(-delta / Lh) - delta
+               + np.log1p(np.exp(-2 * s) * np.expm1(-2 * delta) / Dh))
+        Ph = P[hyp]
+        dP_dL[hyp] = Ph * dlnL
+        dP_dk[hyp] = Ph * dlnk
+        omP[hyp] = -np.expm1(lnP)
+    return P.reshape(shp), dP_dL.reshape(shp), dP_dk.reshape(shp), omP.reshape(shp)
 
 
 def integral_exact(lam, a, k, zeta):
@@ -211,7 +247,7 @@ def integral_exact(lam, a, k, zeta):
     with the phase reading (Psi multiplied by cos zeta)."""
     lam = np.asarray(lam, np.float64)
     a = np.asarray(a, np.float64)
-    P, _, _ = psi(lam * (1 + a), k)
+    P = psi(lam * (1 + a), k)[0]
     return PI * (-np.expm1(-2 * lam)) / (lam * np.sqrt(1 + a)) * (1 + np.cos(zeta) * P)
 
 
@@ -222,14 +258,17 @@ def norm_exact(lam, a, k, zeta):
     k = np.asarray(k, np.float64)
     zeta = np.asarray(zeta, np.float64)
     Lam = lam * (1 + a)
-    P, dP_dL, dP_dk = psi(Lam, k)
+    P, dP_dL, dP_dk, omP = psi(Lam, k)
     Dl = -np.expm1(-2 * lam)
     sq = np.sqrt(1 + a)
     A = PI * Dl / (lam * sq)
     dA_dlam = PI / sq * (2 * np.exp(-2 * lam) * lam - Dl) / lam ** 2
     dA_da = -A / (2 * (1 + a))
     cz, sz = np.cos(zeta), np.sin(zeta)
-    B = 1 + cz * P
+    # B = 1 + cos(zeta) Psi; where cos(zeta) < 0 it is formed as
+    # 2 cos^2(zeta/2) + |cos zeta| (1 - Psi), two terms of one sign (B -> 0
+    # as zeta -> pi with k -> 0, where 1 + cos(zeta) Psi would cancel)
+    B = np.where(cz < 0, 2 * np.cos(zeta / 2) ** 2 - cz * omP, 1 + cz * P)
     dB_dlam = cz * dP_dL * (1 + a)
     dB_da = cz * dP_dL * lam
     dB_dk = cz * dP_dk
@@ -292,20 +331,36 @@ def lobe_terms(d, ax, az, shape, Cn):
     Cn = Cn[:, None, :]
     dx = np.einsum("vnc,knc->kvn", d, ax)
     dz = np.einsum("vnc,knc->kvn", d, az)
+    # 1 - d.z and 1 + d.z as half squared chords |d -+ z|^2 / 2 (the same
+    # numbers for unit vectors). Each stays relatively accurate where it is
+    # small, next to the lobe axis and next to its antipode, where 1 -+ d.z
+    # would subtract two nearly equal numbers; kappa = (1 + d.z)/2,
+    # 1 - (d.z)^2 = (1 - d.z)(1 + d.z) and ln kappa are all formed from them.
+    hp = 0.5 * ((d[None] - az[:, None]) ** 2).sum(-1)
+    hm = 0.5 * ((d[None] + az[:, None]) ** 2).sum(-1)
     with np.errstate(all="ignore"):
-        kappa = (dz + 1) / 2
-        den = 1 - dz * dz
+        kappa = hm / 2
+        den = hp * hm                               # 1 - (d.z)^2
         at_pole = den == 0                          # d = +z or d = -z
-        anti = kappa == 0                           # d = -z
+        anti = hm == 0                              # d = -z
         tau = np.where(at_pole, 0.0, a * dx * dx / den)
-        lnk = np.where(anti, 0.0, np.log(np.where(anti, 1.0, kappa)))
+        # ln kappa = ln(1 - hp/2): log1p where kappa is near 1
+        lnk = np.where(anti, 0.0, np.where(hp < 1.0, np.log1p(-hp / 2),
+                                           np.log(np.where(anti, 1.0, kappa))))
         E = np.where(anti, 0.0, np.exp(tau * lnk))  # kappa^tau
-        p = np.exp(2 * lam * (E * kappa - 1))
+        # E kappa - 1 = e^{(1 + tau) ln kappa} - 1
+        em1 = np.where(anti, -1.0, np.expm1((1 + tau) * lnk))
+        p = np.exp(2 * lam * em1)
         arg = k * dx + zeta
-        carrier = (1 + np.cos(arg)) / 2
+        # (1 + cos t)/2 = cos^2(t/2) and (sin t)/2 = sin(t/2) cos(t/2): the
+        # half-angle forms stay relatively accurate at the carrier's zeros,
+        # where 1 + cos t would cancel
+        c_half, s_half = np.cos(arg / 2), np.sin(arg / 2)
+        carrier = c_half * c_half
+        half_sin = s_half * c_half                   # (sin arg) / 2
         G = np.where(anti, 0.0, p * E * Cn * carrier)
-    return dict(dx=dx, dz=dz, kappa=kappa, den=den, tau=tau, lnk=lnk, E=E, p=p,
-                arg=arg, carrier=carrier, G=G, lam=lam, a=a, k=k, zeta=zeta, Cn=Cn,
+    return dict(dx=dx, dz=dz, kappa=kappa, den=den, tau=tau, lnk=lnk, E=E, p=p, em1=em1,
+                arg=arg, carrier=carrier, half_sin=half_sin, G=G, lam=lam, a=a, k=k, zeta=zeta, Cn=Cn,
                 at_pole=at_pole, anti=anti)
 
 
@@ -367,7 +422,7 @@ def frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm, means=None, 
     p, E, kappa, lnk, tau = t["p"], t["E"], t["kappa"], t["lnk"], t["tau"]
     dx, dz, den, carrier, arg = t["dx"], t["dz"], t["den"], t["carrier"], t["arg"]
     Cnb = t["Cn"]
-    sin_arg = np.sin(arg)
+    half_sin = t["half_sin"]                         # (sin arg) / 2
     dlam_b = dC_dlam[:, None, :]
     da_b = dC_da[:, None, :]
     dk_b = dC_dk[:, None, :]
@@ -382,11 +437,11 @@ def frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm, means=None, 
         ga_terms = [dp_da * E * Cnb * carrier, p * dE_da * Cnb * carrier,
                     p * E * da_b * carrier]
         # --- lambda (sign-corrected dC/dlam for APPROX; dN/dlam for EXACT)
-        dp_dlam = 2 * p * (E * kappa - 1)
+        dp_dlam = 2 * p * t["em1"]
         gl_terms = [E * Cnb * dp_dlam * carrier, E * p * dlam_b * carrier]
         # --- k and zeta (carrier, plus the EXACT normaliser's dependence)
-        dcar_dk = -(dx / 2) * sin_arg
-        dcar_dz = -0.5 * sin_arg
+        dcar_dk = -dx * half_sin
+        dcar_dz = -half_sin
         gk_terms = [p * E * Cnb * dcar_dk, p * E * dk_b * carrier]
         gz_terms = [p * E * Cnb * dcar_dz, p * E * dz_b * carrier]
         # --- x: every term is a multiple of d; collect the scalar factors
@@ -394,7 +449,7 @@ def frame_forward_backward(ax, az, shape, rgbw, c0, grad_rgb, norm, means=None, 
         dE_dx_s = E * lnk * dtau_dx_s
         dp_dx_s = 2 * lam * p * kappa * dE_dx_s
         gx_terms = [dp_dx_s * E * Cnb * carrier, p * dE_dx_s * Cnb * carrier,
-                    p * E * Cnb * (-(k / 2) * sin_arg)]
+                    p * E * Cnb * (-k * half_sin)]
         # --- z
         dkap_dz_s = 0.5
         dtau_dz_s = np.where(pole, 0.0, a * dx * dx * 2 * dz / safe_den ** 2)

@@ -82,7 +82,7 @@ def test_fibonacci_unit_mass_random_frame():
 
 def test_psi_at_k0_is_one():
     L = np.array([1e-3, 0.5, 1.0, 7.0, 300.0, 1e6])
-    P, dPL, dPk = R.psi(L, np.zeros_like(L))
+    P, dPL, dPk, _ = R.psi(L, np.zeros_like(L))
     np.testing.assert_allclose(P, 1.0, rtol=1e-13)
     np.testing.assert_allclose(dPL, 0.0, atol=1e-12)
     np.testing.assert_allclose(dPk, 0.0, atol=1e-12)
