@@ -368,13 +368,33 @@ int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
                     float* grad_colors, float* grad_opac, float* grad_means,
                     float* grad_scales, float* grad_rots, void* stream);
 
+/* ---- achievable HBM rate (measurement) -------------------------------------
+ * Streams `bytes` (a multiple of 16) through HBM with plain 16-byte accesses:
+ * NASG_STREAM_READ reads src (dst: at least 16 bytes, written only in a case
+ * that no real buffer produces, so the reads cannot be optimised away),
+ * NASG_STREAM_WRITE writes dst, NASG_STREAM_COPY copies src to dst (both
+ * `bytes` long, not overlapping). `blocks` 256-thread blocks (1..2^20) stride
+ * over the buffer, each thread keeping `unroll` (1, 2, 4 or 8) accesses in
+ * flight; `nontemporal` (0 or 1) marks the accesses as streaming. Pointers
+ * are device pointers, 16-byte aligned. Asynchronous on `stream`; nothing is
+ * allocated. Used to measure the HBM ceiling the appearance kernels are
+ * compared with beside the 8 TB/s specification.                            */
+enum { NASG_STREAM_READ = 0, NASG_STREAM_WRITE = 1, NASG_STREAM_COPY = 2 };
+
+int nasg_hbm_stream(int32_t mode, const void* src, void* dst, int64_t bytes, int32_t blocks,
+                    int32_t unroll, int32_t nontemporal, void* stream);
+
 /* Human-readable name of a status code (static storage).                    */
 const char* nasg_status_string(int status);
 
 /* ---- launch tuning --------------------------------------------------------
  * The evaluators map each primitive to `lanes` consecutive lanes of a
- * wavefront (1, 2, 4, 8 or 16), each lane owning up to `views_per_lane`
- * views (lanes * views_per_lane >= V). nasg_set_tuning overrides the built-in
+ * wavefront (1, 2, 4, 8 or 16), each lane holding `views_per_lane` views at a
+ * time; V larger than lanes * views_per_lane is processed in chunks of that
+ * many views, accumulated in place, so any pair accepted below serves any V.
+ * The accepted (lanes, views_per_lane) pairs are (1, 1), (1, 2), (1, 4),
+ * (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2) and
+ * (16, 1); others return NASG_ERR_SHAPE. nasg_set_tuning overrides the built-in
  * choice for a (kernel, K, V, dtype) key; nasg_get_tuning reports the choice
  * that a call with that key would use. kernel: 0 = NASG forward, 1 = NASG
  * backward / fused, 2 = SH forward, 3 = SH backward. K is ignored for SH.
@@ -383,7 +403,9 @@ const char* nasg_status_string(int status);
 typedef struct nasg_tuning {
   int32_t lanes;
   int32_t views_per_lane;
-  int32_t block;       /* threads per block: 64, 128, 256, 512 or 1024        */
+  int32_t block;       /* threads per block: 64, 128 or 256 (the kernels are
+                          compiled for at most 256; other values return
+                          NASG_ERR_SHAPE)                                     */
 } nasg_tuning;
 
 int nasg_set_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype,

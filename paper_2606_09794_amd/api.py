@@ -57,6 +57,31 @@ def _dev(t: Optional[torch.Tensor], name: str, dtype=torch.float32) -> Optional[
     return t
 
 
+def _out(t: Optional[torch.Tensor], name: str, shape) -> Optional[torch.Tensor]:
+    """A caller-supplied output buffer: float32, on the device, contiguous and
+    of exactly `shape` (the kernels write that many elements through a raw
+    pointer, so a smaller buffer would be overrun)."""
+    if t is None:
+        return None
+    _dev(t, name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _grad_shapes(k: int, n: int):
+    return {"quat": (k, n, 4), "shape": (k, n, 4), "rgbw": (k, 3, n), "c0": (n, 3),
+            "geom": (n, 3)}
+
+
+def _check_grads(grads, k: int, n: int, where: str = "grads") -> None:
+    shapes = _grad_shapes(k, n)
+    for name, t in grads.items():
+        if name not in shapes:
+            raise ValueError(f"{where}: unknown gradient {name!r} (expected {sorted(shapes)})")
+        _out(t, f"{where}[{name}]", shapes[name])
+
+
 def _p(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -115,7 +140,7 @@ def nasg_eval_fwd(quat, shape, rgbw, c0, *, means=None, cams=None, dirs=None, no
     vw, v = _views(n, means, cams, dirs)
     if out is None:
         out = torch.empty((v, n, 3), device=quat.device, dtype=torch.float32)
-    _dev(out, "out")
+    _out(out, "out", (v, n, 3))
     L.check(L.lib().nasg_eval_fwd(C.byref(p), C.byref(vw), _p(out), _norm_code(norm), _stream()),
             "nasg_eval_fwd")
     return out
@@ -142,9 +167,8 @@ def nasg_eval_bwd(quat, shape, rgbw, c0, grad_rgb, *, means=None, cams=None, dir
         raise ValueError("grad_rgb must be [V][N][3]")
     if grads is None:
         grads = nasg_grad_buffers(k, n, quat.device)
-    for name, t in grads.items():
-        _dev(t, f"grads[{name}]")
-    _dev(rgb_out, "rgb_out")
+    _check_grads(grads, k, n)
+    _out(rgb_out, "rgb_out", (v, n, 3))
     g = L.NasgGrads(*(grads[x].data_ptr() if grads.get(x) is not None else None
                       for x in ("quat", "shape", "rgbw", "c0", "geom")))
     L.check(L.lib().nasg_eval_bwd(C.byref(p), C.byref(vw), _p(grad_rgb), C.byref(g), _p(rgb_out),
@@ -164,7 +188,7 @@ def sh3_eval_fwd(sh, *, means=None, cams=None, dirs=None,
     vw, v = _views(n, means, cams, dirs)
     if out is None:
         out = torch.empty((v, n, 3), device=sh.device, dtype=torch.float32)
-    _dev(out, "out")
+    _out(out, "out", (v, n, 3))
     L.check(L.lib().sh3_eval_fwd(_p(sh), n, C.byref(vw), _p(out), _stream()), "sh3_eval_fwd")
     return out
 
@@ -174,6 +198,8 @@ def sh3_eval_bwd(sh, grad_rgb, *, means=None, cams=None, dirs=None,
                  rgb_out: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
     """Gradients w.r.t. sh and the means (or dirs): dict keys sh, geom."""
     _dev(sh, "sh")
+    if sh.dim() != 3 or tuple(sh.shape[:2]) != (16, 3):
+        raise ValueError("sh must be [16][3][N]")
     n = int(sh.shape[2])
     vw, v = _views(n, means, cams, dirs)
     _dev(grad_rgb, "grad_rgb")
@@ -181,7 +207,12 @@ def sh3_eval_bwd(sh, grad_rgb, *, means=None, cams=None, dirs=None,
         raise ValueError("grad_rgb must be [V][N][3]")
     if grads is None:
         grads = {"sh": torch.empty_like(sh), "geom": torch.empty((n, 3), device=sh.device)}
-    _dev(rgb_out, "rgb_out")
+    shapes = {"sh": (16, 3, n), "geom": (n, 3)}
+    for name, t in grads.items():
+        if name not in shapes:
+            raise ValueError(f"grads: unknown gradient {name!r} (expected ['geom', 'sh'])")
+        _out(t, f"grads[{name}]", shapes[name])
+    _out(rgb_out, "rgb_out", (v, n, 3))
     L.check(L.lib().sh3_eval_bwd(_p(sh), n, C.byref(vw), _p(grad_rgb), _p(grads.get("sh")),
                                  _p(grads.get("geom")), _p(rgb_out),
                                  L.GRAD_ACCUMULATE if accumulate else L.GRAD_OVERWRITE,
@@ -196,9 +227,15 @@ class NasgBatchPlan:
     means, cams, grad_rgb, the float32 gradient buffers ``grads`` (dict as
     returned by nasg_grad_buffers) and optionally ``rgb`` [V][N][3]. The plan
     keeps references to every tensor it points at; ``run()`` only launches
-    kernels and can be captured into a CUDA/HIP graph."""
+    kernels and can be captured into a CUDA/HIP graph. ``tile_iters`` and
+    ``blocks_per_cu`` default to the tuner's cached choice (autotune.tune_batch)."""
 
-    def __init__(self, scenes, norm="exact", tile_iters=4, blocks_per_cu=2):
+    def __init__(self, scenes, norm="exact", tile_iters=None, blocks_per_cu=None):
+        if tile_iters is None or blocks_per_cu is None:
+            from .autotune import batch_defaults
+            dt, db = batch_defaults()
+            tile_iters = dt if tile_iters is None else tile_iters
+            blocks_per_cu = db if blocks_per_cu is None else blocks_per_cu
         arr = (L.NasgScene * len(scenes))()
         self._keep = []
         for idx, sc in enumerate(scenes):
@@ -208,6 +245,8 @@ class NasgBatchPlan:
             if tuple(sc["grad_rgb"].shape) != (v, n, 3):
                 raise ValueError("grad_rgb must be [V][N][3]")
             g = sc["grads"]
+            _check_grads(g, k, n, f"scene {idx} grads")
+            _out(sc.get("rgb"), f"scene {idx} rgb", (v, n, 3))
             arr[idx] = L.NasgScene(p, vw, sc["grad_rgb"].data_ptr(),
                                    L.NasgGrads(*(g[x].data_ptr() if g.get(x) is not None else None
                                                  for x in ("quat", "shape", "rgbw", "c0", "geom"))),

@@ -10,6 +10,7 @@ which is harmless.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -20,6 +21,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnasg.so")
+STAMP = LIB + ".srchash"      # hash of the sources the library was built from
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -53,6 +55,29 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def source_hash() -> str:
+    """Hash of every file the library is built from (csrc/ and include/) and of
+    the compiler flags."""
+    flags = [f for i, f in enumerate(HIPCC_FLAGS)
+             if f != "-I" and (i == 0 or HIPCC_FLAGS[i - 1] != "-I")]   # paths differ per machine
+    h = hashlib.sha256(" ".join(flags).encode())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".hpp", ".h")):
+                h.update(f.encode())
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def is_current() -> bool:
+    """True when libnasg.so exists and was built from the present sources."""
+    if not (os.path.exists(LIB) and os.path.exists(STAMP)):
+        return False
+    with open(STAMP) as fh:
+        return fh.read().strip() == source_hash()
+
+
 def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile all HIP sources and link the shared library; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
@@ -66,6 +91,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
     os.replace(tmp, LIB)
+    with open(STAMP, "w") as fh:
+        fh.write(source_hash() + "\n")
     return LIB
 
 

@@ -213,7 +213,9 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             const float qG = gG * G;
             acc_G += qG;
             acc_l = fmaf(qG, em1, acc_l);
-            const float Ek = 1.f + em1;
+            // E kappa itself, not 1 + (E kappa - 1): near d = -z kappa is small and
+            // the FP32 difference would carry its absolute error into E kappa
+            const float Ek = static_cast<float>(Ekd);
             const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
             acc_a = fmaf(qG * T2 * L, u, acc_a);
             const float Sth = (peak ? -scp : scp) * Npe;      // N p E dc/dtheta

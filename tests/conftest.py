@@ -13,12 +13,11 @@ def pytest_configure(config):
 
 
 def pytest_sessionstart(session):
-    """Build libnasg.so (hipcc cross-compiles for gfx950) only when no built
-    library is present, e.g. on a fresh checkout; an existing build is used
-    as it is."""
-    from paper_2606_09794_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
-        from paper_2606_09794_amd import build
+    """Build libnasg.so (hipcc cross-compiles for gfx950) when no library is
+    present or when the one present was built from other sources than the
+    ones in the tree (its stamp holds the hash of csrc/ and include/)."""
+    from paper_2606_09794_amd import build
+    if not build.is_current():
         build.build()
 
 

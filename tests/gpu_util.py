@@ -58,8 +58,14 @@ def oracle_sh(w):
 
 
 def compare(got, ref, scale, name, tol):
-    e = M.scaled_error(got, ref, scale)
-    s = M.summarize(e)
+    """Scaled error (gated at `tol`) and the plain relative error (reported)
+    of one output or gradient; prints both as max / p99 / median."""
+    rep = M.report(got, ref, scale)
+    s = rep["scaled"]
+    p = rep["plain_rel"]
+    print(f"  {name:>12s}: scaled max {s['max']:.2e} p99 {s['p99']:.2e} median {s['median']:.2e}"
+          f" | plain rel max {p['max']:.2e} p99 {p['p99']:.2e} median {p['median']:.2e}"
+          f" ({p['n']} of {s['n']})")
     assert np.isfinite(np.asarray(got)).all(), f"{name}: non-finite values"
     assert s["max"] <= tol, f"{name}: scaled error {s} above {tol}"
     return s

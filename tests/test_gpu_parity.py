@@ -226,3 +226,68 @@ def test_eval_calls_replay_from_a_graph():
         assert torch.isfinite(junk)
         for k, (t, e) in enumerate(zip(outs, eager)):
             assert torch.equal(t, e), (rep, k)
+
+
+def test_sh3_autograd_function():
+    """SH3Eval: forward through sh3_eval_fwd, backward through sh3_eval_bwd,
+    in camera mode (gradient to sh and means) and direction mode (sh, dirs)."""
+    w = W.draw_workload(14, 400, 1, 4)
+    d = upload(w)
+    sh = d["sh"].clone().requires_grad_(True)
+    means = d["means"].clone().requires_grad_(True)
+    rgb = P.SH3Eval.apply(sh, means, d["cams"], None)
+    (rgb * d["grad_rgb"]).sum().backward()
+    ref, scale = oracle_sh(w)
+    compare(rgb.detach().cpu().numpy(), ref["rgb"], scale["rgb"], "rgb", TOL)
+    compare(sh.grad.cpu().numpy(), ref["sh"], scale["sh"], "sh", TOL)
+    compare(means.grad.cpu().numpy(), ref["geom"], scale["geom"], "means", TOL)
+    w0 = W.config0()
+    d0 = upload(w0)
+    sh0 = d0["sh"].clone().requires_grad_(True)
+    dirs = d0["dirs"].clone().requires_grad_(True)
+    rgb0 = P.SH3Eval.apply(sh0, None, None, dirs)
+    (rgb0 * d0["grad_rgb"]).sum().backward()
+    ref0, scale0 = oracle_sh(w0)
+    compare(sh0.grad.cpu().numpy(), ref0["sh"], scale0["sh"], "sh (dirs)", TOL)
+    compare(dirs.grad.cpu().numpy(), ref0["geom"], scale0["geom"], "dirs", TOL)
+
+
+def test_output_buffers_are_shape_checked():
+    """Caller-supplied outputs of the wrong shape, dtype or device are refused
+    on the host before any launch."""
+    w = W.draw_workload(15, 64, 2, 3)
+    d = upload(w)
+    base = dict(means=d["means"], cams=d["cams"])
+    lob = (d["quat"], d["shape"], d["rgbw"], d["c0"])
+    with pytest.raises(ValueError):
+        P.nasg_eval_fwd(*lob, out=torch.empty((1, 64, 3), device="cuda"), **base)
+    with pytest.raises(ValueError):
+        P.nasg_eval_fwd(*lob, out=torch.empty((3, 64, 3), device="cuda", dtype=torch.float64), **base)
+    with pytest.raises(ValueError):
+        P.nasg_eval_fwd(*lob, out=torch.empty((3, 64, 3)), **base)
+    g = P.nasg_grad_buffers(2, 64, "cuda")
+    bad = dict(g, quat=torch.empty((2, 63, 4), device="cuda"))
+    with pytest.raises(ValueError):
+        P.nasg_eval_bwd(*lob, d["grad_rgb"], grads=bad, **base)
+    bad = dict(g, rgbw=torch.empty((2, 64, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        P.nasg_eval_bwd(*lob, d["grad_rgb"], grads=bad, **base)
+    with pytest.raises(ValueError):
+        P.nasg_eval_bwd(*lob, d["grad_rgb"], grads=g, rgb_out=torch.empty((1, 64, 3), device="cuda"),
+                        **base)
+    with pytest.raises(ValueError):
+        P.sh3_eval_bwd(d["sh"], d["grad_rgb"], grads={"sh": torch.empty((16, 3, 63), device="cuda")},
+                       **base)
+    with pytest.raises(ValueError):
+        P.sh3_eval_bwd(d["sh"], d["grad_rgb"], grads={"geom": torch.empty((64, 3))}, **base)
+    with pytest.raises(ValueError):
+        P.sh3_eval_bwd(d["sh"][:15].contiguous(), d["grad_rgb"], **base)
+    with pytest.raises(ValueError):
+        P.sh3_eval_fwd(d["sh"], out=torch.empty((3, 64, 2), device="cuda"), **base)
+    sc = dict(d, grads=dict(g, c0=torch.empty((65, 3), device="cuda")), rgb=None)
+    with pytest.raises(ValueError):
+        P.NasgBatchPlan([sc])
+    sc = dict(d, grads=g, rgb=torch.empty((2, 64, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        P.NasgBatchPlan([sc])
+    torch.cuda.synchronize()
