@@ -105,26 +105,62 @@ def measured_counters(key, files=APPEARANCE_SOURCES):
     return ent
 
 
-def counters_roofline(key, ms, ab, evals, alu):
-    """Roofline object of a launch from the committed counters for `key`: the
-    calibrated HBM bytes as its traffic and, with `alu`, the VALU
-    lane-instruction rate against the issue peak as the bound with the HBM
-    figures beside it. Missing counters, or counters taken on other kernel
-    sources, give the HBM roofline with unknown traffic."""
-    hbm = {"achieved": round(ab / ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": ab}
-    c = measured_counters(key)
-    if c is None:
-        return dict(hbm, bound="hbm", traffic=None)
-    extra = {"profiled_launch": c["profiled_launch"]} if "profiled_launch" in c else {}
-    if not alu:
-        return dict(hbm, bound="hbm", traffic=c["bytes_per_launch"], **extra)
-    lane = c["valu_wave_instructions_per_launch"] * 64
-    ach = lane / (ms * 1e-3) / 1e12
-    return dict({"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
-                 "unit": "T VALU lane-instructions/s", "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
-                 "traffic": c["bytes_per_launch"], "lane_instructions_per_eval": round(lane / evals, 1),
-                 "hbm": hbm}, **extra)
+# Algorithmic arithmetic of the path: floating-point operations its formulas
+# need (an add, multiply, fused multiply-add, reciprocal, square root or
+# transcendental counts 1; no extra precision, no index or conversion work).
+OPS_LOBE_VIEW = 26 + 46      # value and colour; backward partials and their sums
+OPS_LOBE = {"exact": 23 + 62 + 41, "approx": 23 + 13 + 41}   # frame, normaliser, write-out
+OPS_VIEW = 22                # direction, c0 and mean gradients per primitive-view
+
+
+def algorithmic_ops_per_eval(k, v, norm="exact"):
+    """Operations per primitive-view of the fused forward+backward."""
+    return k * OPS_LOBE_VIEW + k * OPS_LOBE[norm] / v + OPS_VIEW
+
+
+def roofline(key, ms, ab, evals, ops_per_eval=None, files=APPEARANCE_SOURCES, kernel=None,
+             ceiling=None):
+    """Roofline object of one launch: the algorithmic bytes against the HBM peak
+    (`frac`), the counter-measured traffic when the committed counters match the
+    kernel sources, the VALU issue rate from those counters and the algorithmic
+    operation rate against the non-packed issue peak, and which roof binds."""
+    ach = ab / ms / 1e6
+    r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+         "algorithmic_bytes_per_launch": int(ab), "bytes_per_eval": round(ab / evals, 2)}
+    if kernel:
+        r["kernel"] = kernel
+    if ceiling:
+        r["stream_ceiling_GB_s"] = ceiling
+        r["frac_of_stream_ceiling"] = round(ach / ceiling, 4)
+    peak = VALU_PEAK_LANE_OPS / 1e12
+    fracs = {"hbm": ach / HBM_PEAK_GBS}
+    if ops_per_eval is not None:
+        t = ops_per_eval * evals / (ms * 1e-3) / 1e12
+        r["algorithmic_ops"] = {"ops_per_eval": round(ops_per_eval, 1), "achieved": round(t, 2),
+                                "peak": round(peak, 2), "unit": "T ops/s", "frac": round(t / peak, 4)}
+    c = measured_counters(key, files)
+    if c is not None:
+        r["traffic"] = c["bytes_per_launch"]
+        lane = c["valu_wave_instructions_per_launch"] * 64
+        t = lane / (ms * 1e-3) / 1e12
+        r["valu_issue"] = {"lane_instructions_per_eval": round(lane / evals, 1), "achieved": round(t, 2),
+                           "peak": round(peak, 2), "unit": "T VALU lane-instructions/s",
+                           "frac": round(t / peak, 4)}
+        if "clock_GHz" in c:
+            r["valu_issue"]["profiled_clock_GHz"] = c["clock_GHz"]
+        if "profiled_launch" in c:
+            r["profiled_launch"] = c["profiled_launch"]
+        fracs["valu"] = t / peak
+    r["binding"] = max(fracs, key=fracs.get)
+    return r
+
+
+def parity_report(got, ref, scale):
+    """max / p99 / median of the scaled error (the gate, <= 1e-5) and of the
+    plain relative error per output and gradient."""
+    from oracle import metrics as M
+    return {k: M.report(got[k], ref[k], scale[k]) for k in got}
 
 
 # ----------------------------------------------------------------- CPU oracle
@@ -141,12 +177,35 @@ def _oracle_chunk(args):
     return w.n * w.v
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_cores():
+    """Worker processes for the CPU leg: the cores this process may run on,
+    capped at the CPU share the host grants a one-GPU job (OMP_NUM_THREADS when
+    set: the GPU hosts export their share there; the affinity mask there shows
+    the whole machine)."""
+    aff = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    cap = int(share) if share.isdigit() and int(share) > 0 else aff
+    return max(1, min(aff, cap)), aff
+
+
 def cpu_baseline(w_full, prims=1_000_000, chunk=1024, norm_code=0):
     """Time the FP64 oracle (as written) on the first `prims` primitives of the
     workload, split over the host's cores (forked workers share the arrays)."""
     global _CPU_W
     _CPU_W = w_full
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    cores, aff = host_cores()
     n = min(prims, w_full.n)
     ranges = [(i, min(i + chunk, n), norm_code) for i in range(0, n, chunk)]
     ctx = mp.get_context("fork")
@@ -160,7 +219,7 @@ def cpu_baseline(w_full, prims=1_000_000, chunk=1024, norm_code=0):
             "sample": f"FP64 NumPy oracle, fused fwd+bwd on the first {n} of {w_full.n} primitives x "
                       f"{w_full.v} views (K={w_full.k}), {len(ranges)} chunks of {chunk} over "
                       f"{cores} processes, {dt:.1f} s wall",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu_model(), "affinity_cores": aff}
 
 
 # ----------------------------------------------------------------------- GPU
@@ -195,9 +254,8 @@ def time_launches(fn, steps, warmup):
 
 
 def copy_ceiling(steps, mib=1024):
-    """The achievable HBM rate beside the 8 TB/s spec: a plain device-to-device
-    copy of `mib` MiB (the runtime's copy kernel), each byte read once and
-    written once."""
+    """The runtime's own device-to-device copy of `mib` MiB (each byte read once
+    and written once), kept beside the hand-written streaming kernels."""
     import torch
     src = torch.empty(mib << 18, device="cuda")
     dst = torch.empty_like(src)
@@ -208,27 +266,56 @@ def copy_ceiling(steps, mib=1024):
             "frac_of_peak": round(cb / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
-def sampled_parity(w, d, g, rgb, norm, n_sample=512, seed=0):
-    """Oracle on sampled primitives of the full-size run (all views, all lobes)."""
-    import workloads as W
-    from oracle import metrics as M
-    from oracle import nasg_ref as R
-    idx = np.sort(np.random.default_rng(seed).choice(w.n, size=min(n_sample, w.n), replace=False))
-    sub = W.take_primitives(w, idx)
-    code = R.NORM_EXACT if norm == "exact" else R.NORM_APPROX
-    ref, scale = R.forward_backward(sub.quat, sub.shape, sub.rgbw, sub.c0, sub.grad_rgb, code,
-                                    means=sub.means, cams=sub.cams)
-    ref["geom"], scale["geom"] = ref.pop("means"), scale.pop("means")
-    got = {"rgb": rgb[:, idx].cpu().numpy(), "quat": g["quat"][:, idx].cpu().numpy(),
-           "shape": g["shape"][:, idx].cpu().numpy(), "rgbw": g["rgbw"][:, :, idx].cpu().numpy(),
-           "c0": g["c0"][idx].cpu().numpy(), "geom": g["geom"][idx].cpu().numpy()}
-    return {k: M.summarize(M.scaled_error(got[k], ref[k], scale[k]))["max"] for k in got}
+STREAM_GRID = (256, 512, 1024, 2048, 4096, 8192)     # 256-thread blocks (1..32 per CU)
+STREAM_UNROLL = (1, 2, 4, 8)
+
+
+def stream_ceiling(gib=2, reps=3):
+    """Achievable HBM rate from the library's hand-written streaming kernels
+    (16 B per lane): read-only, write-only and copy of `gib` GiB buffers (far
+    beyond the 256 MB of last-level cache), swept over grid size, accesses in
+    flight per thread and nontemporal hints; each point is the mean of `reps`
+    launches after one warm-up. Returns the best point per mode and the sweep."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2606_09794_amd import _lib as L
+    nbytes = gib << 30
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    lib = L.lib()
+    out, sweep = {}, {}
+    for mode, name, moved in ((L.STREAM_READ, "read", nbytes), (L.STREAM_WRITE, "write", nbytes),
+                              (L.STREAM_COPY, "copy", 2 * nbytes)):
+        best = None
+        for grid in STREAM_GRID:
+            for unroll in STREAM_UNROLL:
+                for nt in (0, 1):
+                    run = lambda: L.check(lib.nasg_hbm_stream(  # noqa: E731
+                        mode, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, grid,
+                        unroll, nt, stream), "nasg_hbm_stream")
+                    ms = time_launches(run, reps, 1)
+                    gbs = moved / ms / 1e6
+                    sweep[f"{name}_g{grid}_u{unroll}_nt{nt}"] = round(gbs, 1)
+                    if best is None or gbs > best["GB_s"]:
+                        best = {"GB_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                "ms": round(ms, 4), "bytes": moved, "blocks": grid,
+                                "unroll": unroll, "nontemporal": nt}
+        out[name] = best
+    del src, dst
+    torch.cuda.empty_cache()
+    return out, sweep
 
 
 def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
-    """Max scaled error of device results `got` (full tensors) on sampled primitives,
-    against the oracle on the stored values (or, with orig=True, on the float32 values
-    before bf16 rounding: the quantisation cost)."""
+    """Error of device results `got` (full tensors) on sampled primitives (all
+    their views and lobes) against the oracle on the stored values: max / p99 /
+    median of the scaled error (the gate) and of the plain relative error per
+    output and gradient. With orig=True the oracle takes the float32 values
+    before bf16 rounding instead (the quantisation cost: scaled-error summary
+    and the fraction of elements within 2e-2)."""
     import workloads as W
     from oracle import metrics as M
     from oracle import nasg_paper as Pp
@@ -251,10 +338,18 @@ def _sampled(w, got, norm, n_sample=256, seed=0, orig=False):
            "rgbw": lambda t: t[:, :, idx], "c0": lambda t: t[idx], "geom": lambda t: t[idx]}
     out = {}
     for k, f in sel.items():
-        e = M.scaled_error(f(got[k]).cpu().numpy(), ref[k], scale[k])
-        out[k] = {"max": float(e.max()), "p99": float(np.percentile(e, 99)),
-                  "frac_within_2e-2": float((e <= 2e-2).mean())} if orig else float(e.max())
+        y = f(got[k]).cpu().numpy()
+        if orig:
+            e = M.scaled_error(y, ref[k], scale[k])
+            out[k] = dict(M.summarize(e), frac_within_2e_2=float((e <= 2e-2).mean()))
+        else:
+            out[k] = M.report(y, ref[k], scale[k])
     return out
+
+
+def worst_scaled(rep):
+    """The largest scaled error over the outputs of a parity report."""
+    return max(v["scaled"]["max"] for v in rep.values())
 
 
 def profile_other(args, log):
@@ -305,8 +400,165 @@ def profile_other(args, log):
                           source_hash=kernel_source_hash(), **info)), flush=True)
 
 
+def measure_single_camera(norm, steps, warmup, log, n=1 << 20, ceiling=None):
+    """K = 8, 1 M primitives x one camera, fused forward+backward (FP32
+    storage), with the degree-3 SH fused launch on the same inputs."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    t0 = time.perf_counter()
+    w = W.config1(n=n)
+    log(f"single camera: generated N={w.n} K={w.k} in {time.perf_counter() - t0:.1f}s")
+    d = upload(w)
+    n, k, v = w.n, w.k, w.v
+    g = P.nasg_grad_buffers(k, n, "cuda")
+    rgb = torch.empty((v, n, 3), device="cuda")
+    fn = lambda: P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],  # noqa: E731
+                                 means=d["means"], cams=d["cams"], norm=norm, grads=g, rgb_out=rgb)
+    ms = time_launches(fn, steps, warmup)
+    ab = algorithmic_bytes(n, k, v)
+    gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
+    rsh = torch.empty_like(rgb)
+    msh = time_launches(lambda: P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"],
+                                               grads=gsh, rgb_out=rsh), steps, warmup)
+    fn()
+    torch.cuda.synchronize()
+    par = _sampled(w, dict(g, rgb=rgb), norm)
+    log(f"single camera: {ms:.4f} ms, parity worst scaled {worst_scaled(par):.2e}")
+    sb = sh_bytes(n, v)
+    return {"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x 1 camera, FP32, {norm} normaliser",
+            "ms": round(ms, 4), "G_evals_s": round(n * v / ms / 1e6, 4),
+            "roofline": roofline(f"nasg_fused_k{k}_v{v}_n{n}_{norm}", ms, ab, n * v,
+                                 algorithmic_ops_per_eval(k, v, norm), ceiling=ceiling,
+                                 kernel="nasg_kernel (fused forward+backward, one view)"),
+            "sh3_fused": {"ms": round(msh, 4), "G_evals_s": round(n * v / msh / 1e6, 4),
+                          "GB_s": round(sb / msh / 1e6, 1), "hbm_frac": round(sb / msh / 1e6 / HBM_PEAK_GBS, 4)},
+            "parity_sampled": par}
+
+
+def measure_bf16_k16(norm, steps, warmup, log, n=6_000_000, ceiling=None):
+    """K = 16, 6 M primitives x 8 cameras with bf16 lobe storage, beside the
+    same values in FP32 storage; parity against the dequantised values (the
+    gate) and the quantisation cost against the FP32 values before rounding."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    t0 = time.perf_counter()
+    w = W.config3(n=n)
+    log(f"bf16 K=16: generated N={w.n} K={w.k} V={w.v} in {time.perf_counter() - t0:.1f}s")
+    d = upload(w)
+    n, k, v = w.n, w.k, w.v
+    g = P.nasg_grad_buffers(k, n, "cuda")
+    rgb = torch.empty((v, n, 3), device="cuda")
+    fn = lambda dd: P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],  # noqa: E731
+                                    means=dd["means"], cams=dd["cams"], norm=norm, grads=g, rgb_out=rgb)
+    ms = time_launches(lambda: fn(d), steps, warmup)
+    fn(d)
+    torch.cuda.synchronize()
+    par = _sampled(w, dict(g, rgb=rgb), norm)
+    qcost = _sampled(w, dict(g, rgb=rgb), norm, orig=True)
+    d32 = dict(d, quat=d["quat"].float(), shape=d["shape"].float(), rgbw=d["rgbw"].float())
+    ms32 = time_launches(lambda: fn(d32), steps, warmup)
+    fn(d32)
+    torch.cuda.synchronize()
+    par32 = _sampled(w, dict(g, rgb=rgb), norm)
+    log(f"bf16 K=16: {ms:.3f} ms (fp32 storage {ms32:.3f} ms), parity worst scaled "
+        f"{worst_scaled(par):.2e}")
+    ab = algorithmic_bytes(n, k, v, lobe_bytes=LOBE_BYTES_BF16)
+    ab32 = algorithmic_bytes(n, k, v)
+    return {"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, lobe parameters "
+                        f"stored in bf16, {norm} normaliser",
+            "ms": round(ms, 4), "G_evals_s": round(n * v / ms / 1e6, 4),
+            "roofline": roofline(f"nasg_fused_k{k}_v{v}_n{n}_{norm}_bf16", ms, ab, n * v,
+                                 algorithmic_ops_per_eval(k, v, norm), ceiling=ceiling,
+                                 kernel="nasg_kernel (fused forward+backward, bf16 lobes)"),
+            "fp32_storage_same_values": {
+                "ms": round(ms32, 4), "G_evals_s": round(n * v / ms32 / 1e6, 4),
+                "hbm_frac": round(ab32 / ms32 / 1e6 / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": ab32, "parity_sampled": par32},
+            "parity_sampled": par,
+            "bf16_quantisation_cost_vs_fp32_values": qcost}
+
+
+def measure_uneven_batch(norm, steps, warmup, log, ceiling=None, tune=True):
+    """32 scenes (N log-uniform in [5e4, 2e6], K in {4, 8, 16}, V in {1, 4, 16})
+    in one persistent fused launch with the tuner's (tile passes, blocks per CU),
+    its hipGraph replay and per-scene launches; sampled parity per scene."""
+    import torch
+
+    import paper_2606_09794_amd as P
+    import workloads as W
+    from paper_2606_09794_amd import autotune
+    t0 = time.perf_counter()
+    scenes = W.config4()
+    log(f"uneven batch: generated {len(scenes)} scenes, {sum(s.workload.n for s in scenes)} primitives "
+        f"in {time.perf_counter() - t0:.1f}s")
+    dev = []
+    for sc in scenes:
+        w = sc.workload
+        dd = upload(w)
+        dd["grads"] = P.nasg_grad_buffers(w.k, w.n, "cuda")
+        dd["rgb"] = torch.empty((w.v, w.n, 3), device="cuda")
+        dev.append(dd)
+    evals = sum(sc.workload.n * sc.workload.v for sc in scenes)
+    ab = sum(algorithmic_bytes(sc.workload.n, sc.workload.k, sc.workload.v) for sc in scenes)
+    ops = sum(algorithmic_ops_per_eval(sc.workload.k, sc.workload.v, norm) * sc.workload.n * sc.workload.v
+              for sc in scenes) / evals
+    if tune:
+        choice = autotune.tune_batch(dev, norm=norm, save=False, verbose=False)
+        ti, bpc, sweep = choice["tile_iters"], choice["blocks_per_cu"], choice["sweep_ms"]
+    else:
+        ti, bpc = autotune.batch_defaults()
+        sweep = None
+    plan = P.NasgBatchPlan(dev, norm=norm, tile_iters=ti, blocks_per_cu=bpc)
+    ms = time_launches(plan.run, steps, warmup)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        plan.run()
+    ms_graph = time_launches(graph.replay, steps, warmup)
+
+    def per_scene():
+        for dd in dev:
+            P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],
+                            means=dd["means"], cams=dd["cams"], norm=norm, grads=dd["grads"],
+                            rgb_out=dd["rgb"])
+    ms_sep = time_launches(per_scene, steps, warmup)
+    graph.replay()
+    torch.cuda.synchronize()
+    worst = {}
+    for sc, dd in zip(scenes[::4], dev[::4]):
+        rep = _sampled(sc.workload, dict(dd["grads"], rgb=dd["rgb"]), norm, n_sample=64)
+        for kk, vv in rep.items():
+            cur = worst.get(kk)
+            if cur is None or vv["scaled"]["max"] > cur["scaled"]["max"]:
+                worst[kk] = vv
+    log(f"uneven batch: persistent {ms:.3f} ms, graph {ms_graph:.3f} ms, per-scene {ms_sep:.3f} ms "
+        f"(tile {ti}, {bpc} blocks/CU), parity worst scaled {worst_scaled(worst):.2e}")
+    del graph, plan, dev
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(scenes)} scenes (N log-uniform in [5e4, 2e6], K in {{4,8,16}}, "
+                        f"V in {{1,4,16}}), one persistent fused fwd+bwd launch, {norm} normaliser",
+            "scenes": len(scenes), "primitives": sum(s.workload.n for s in scenes), "evals": evals,
+            "tile_iters": ti, "blocks_per_cu": bpc,
+            "ms": round(ms, 4), "G_evals_s": round(evals / ms / 1e6, 4),
+            "roofline": roofline(f"nasg_batch_uneven{len(scenes)}_{norm}", ms, ab, evals, ops,
+                                 ceiling=ceiling, kernel="nasg_batched_kernel (persistent)"),
+            "graph_replay": {"ms": round(ms_graph, 4), "G_evals_s": round(evals / ms_graph / 1e6, 4)},
+            "per_scene_launches": {"ms": round(ms_sep, 4), "G_evals_s": round(evals / ms_sep / 1e6, 4)},
+            "tuner_sweep_ms": sweep,
+            "parity_sampled_worst_scene": worst}
+
+
 def bench_other(args, log):
-    """Workloads other than the headline: single camera, bf16 K=16, uneven batch."""
+    """Workloads other than the headline, each as its own JSON line."""
     import torch
 
     import paper_2606_09794_amd as P
@@ -317,63 +569,20 @@ def bench_other(args, log):
     res = {"metric": METRIC, "unit": "G evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic"}
+
+    def line(m, dtype, **cfg):
+        res.update(value=m["G_evals_s"], ms_per_step=m["ms"], dtype=dtype,
+                   config=dict({"workload": m["workload"]}, **cfg), roofline=m["roofline"],
+                   detail={k: v for k, v in m.items() if k not in ("roofline", "workload")})
+
     if args.workload == "single-camera":
-        w = W.config1(n=args.n)
-        d = upload(w)
-        n, k, v = w.n, w.k, w.v
-        g = P.nasg_grad_buffers(k, n, "cuda")
-        rgb = torch.empty((v, n, 3), device="cuda")
-        fn = lambda: P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],  # noqa: E731
-                                     means=d["means"], cams=d["cams"], norm=args.norm, grads=g, rgb_out=rgb)
-        ms = time_launches(fn, args.steps, args.warmup)
-        ab = algorithmic_bytes(n, k, v)
-        gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
-        msh = time_launches(lambda: P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"],
-                                                   grads=gsh, rgb_out=rgb), args.steps, args.warmup)
-        fn()
-        torch.cuda.synchronize()
-        res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
-                   config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x 1 camera, FP32, "
-                                       f"{args.norm} normaliser", "primitives": n, "lobes": k, "views": v},
-                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", ms, ab, n * v,
-                                              alu=False),
-                   compare={"sh3_fused": {"ms": round(msh, 4), "G_evals_s": round(n * v / msh / 1e6, 4),
-                                          "hbm_frac": round(sh_bytes(n, v) / msh / 1e6 / HBM_PEAK_GBS, 4)},
-                            "hbm_copy_ceiling": copy_ceiling(args.steps)},
-                   parity_sampled_max_scaled_error=_sampled(w, dict(g, rgb=rgb), args.norm))
-        rf = res["roofline"]
-        rf["copy_ceiling_GB_s"] = res["compare"]["hbm_copy_ceiling"]["GB_s"]
-        rf["frac_of_copy_ceiling"] = round(rf["achieved"] / rf["copy_ceiling_GB_s"], 4)
+        line(measure_single_camera(args.norm, args.steps, args.warmup, log, n=args.n), "f32",
+             primitives=args.n, lobes=8, views=1)
     elif args.workload == "bf16-k16":
-        w = W.config3(n=args.n)
-        log(f"generated N={w.n} K={w.k} V={w.v} bf16")
-        d = upload(w)
-        n, k, v = w.n, w.k, w.v
-        g = P.nasg_grad_buffers(k, n, "cuda")
-        rgb = torch.empty((v, n, 3), device="cuda")
-        fn = lambda dd: P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],  # noqa: E731
-                                        means=dd["means"], cams=dd["cams"], norm=args.norm, grads=g,
-                                        rgb_out=rgb)
-        ms = time_launches(lambda: fn(d), args.steps, args.warmup)
-        fn(d)
-        torch.cuda.synchronize()
-        par = _sampled(w, dict(g, rgb=rgb), args.norm)
-        qcost = _sampled(w, dict(g, rgb=rgb), args.norm, orig=True)
-        d32 = dict(d, quat=d["quat"].float(), shape=d["shape"].float(), rgbw=d["rgbw"].float())
-        ms32 = time_launches(lambda: fn(d32), args.steps, args.warmup)
-        ab = algorithmic_bytes(n, k, v, lobe_bytes=LOBE_BYTES_BF16)
-        ab32 = algorithmic_bytes(n, k, v)
-        res.update(value=round(n * v / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32 (bf16 storage)",
-                   config={"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
-                                       f"lobe parameters stored in bf16, {args.norm} normaliser",
-                           "primitives": n, "lobes": k, "views": v},
-                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}_bf16", ms, ab,
-                                              n * v, alu=True),
-                   compare={"fp32_storage_same_values": {"ms": round(ms32, 4),
-                                                         "G_evals_s": round(n * v / ms32 / 1e6, 4),
-                                                         "algorithmic_bytes_per_launch": ab32}},
-                   parity_sampled_max_scaled_error=par,
-                   bf16_quantisation_cost_vs_fp32_values=qcost)
+        line(measure_bf16_k16(args.norm, args.steps, args.warmup, log, n=args.n), "f32 (bf16 storage)",
+             primitives=args.n, lobes=16, views=8)
+    elif args.workload == "uneven-batch":
+        line(measure_uneven_batch(args.norm, args.steps, args.warmup, log), "f32", scenes=32)
     elif args.workload == "paper-params":
         t0 = time.perf_counter()
         w = W.draw_workload(7, args.n, 8, args.views, with_sh=False, param="angles")
@@ -399,11 +608,11 @@ def bench_other(args, log):
                                        f"the paper's raw lobe values (three frame cosines and "
                                        f"activations), FP32, {args.norm} normaliser",
                            "primitives": n, "lobes": k, "views": v, "param": "angles"},
-                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}_angles", ms, ab,
-                                              n * v, alu=True),
+                   roofline=roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}_angles", ms, ab, n * v,
+                                     kernel="nasg_kernel (fused, the paper's raw values)"),
                    compare={"quaternion_parametrisation_same_sizes": {
                        "ms": round(msq, 4), "G_evals_s": round(n * v / msq / 1e6, 4)}},
-                   parity_sampled_max_scaled_error=par)
+                   parity_sampled=par)
     elif args.workload == "families":
         per = {}
         n, k, v = args.n, 8, args.views
@@ -421,10 +630,10 @@ def bench_other(args, log):
             ms = time_launches(fn, args.steps, args.warmup)
             fn()
             torch.cuda.synchronize()
+            rep = _sampled(w, dict(g, rgb=rgb), args.norm, n_sample=128)
             per[fam] = {"ms": round(ms, 4), "G_evals_s": round(n * v / ms / 1e6, 4),
                         "hbm_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
-                        "parity_sampled_max_scaled_error": _sampled(w, dict(g, rgb=rgb), args.norm,
-                                                                    n_sample=128)}
+                        "parity_sampled_max_scaled_error": worst_scaled(rep)}
             del d
         best = per["nasgabor"]
         res.update(value=best["G_evals_s"], ms_per_step=best["ms"], dtype="f32",
@@ -432,71 +641,10 @@ def bench_other(args, log):
                                        f"{n} primitives x {v} cameras each, FP32; value = NASGabor",
                            "primitives": n, "lobes": k, "views": v},
                    # the NASGabor launch is the headline's kernel at the headline's sizes
-                   roofline=counters_roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", best["ms"], ab,
-                                              n * v, alu=True),
+                   roofline=roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", best["ms"], ab, n * v,
+                                     algorithmic_ops_per_eval(k, v, args.norm),
+                                     kernel="nasg_kernel (fused forward+backward)"),
                    families=per)
-    elif args.workload == "uneven-batch":
-        t0 = time.perf_counter()
-        scenes = W.config4()
-        log(f"generated {len(scenes)} scenes, {sum(s.workload.n for s in scenes)} primitives in "
-            f"{time.perf_counter() - t0:.1f}s")
-        dev = []
-        for sc in scenes:
-            w = sc.workload
-            dd = upload(w)
-            dd["grads"] = P.nasg_grad_buffers(w.k, w.n, "cuda")
-            dd["rgb"] = torch.empty((w.v, w.n, 3), device="cuda")
-            dev.append(dd)
-        evals = sum(sc.workload.n * sc.workload.v for sc in scenes)
-        ab = sum(algorithmic_bytes(sc.workload.n, sc.workload.k, sc.workload.v) for sc in scenes)
-        # the project's tuner: sweep tile size and persistent blocks per CU
-        sweep = []
-        for ti in (1, 2, 4, 8, 16):
-            for bpc in (1, 2, 4):
-                plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=ti, blocks_per_cu=bpc)
-                m = time_launches(plan.run, 3, 1)
-                sweep.append((m, ti, bpc))
-        m_best, ti, bpc = min(sweep)
-        plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=ti, blocks_per_cu=bpc)
-        ms = time_launches(plan.run, args.steps, args.warmup)
-        graph = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            plan.run()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph):
-            plan.run()
-        ms_graph = time_launches(graph.replay, args.steps, args.warmup)
-
-        def per_scene():
-            for dd in dev:
-                P.nasg_eval_bwd(dd["quat"], dd["shape"], dd["rgbw"], dd["c0"], dd["grad_rgb"],
-                                means=dd["means"], cams=dd["cams"], norm=args.norm, grads=dd["grads"],
-                                rgb_out=dd["rgb"])
-        ms_sep = time_launches(per_scene, max(3, args.steps // 2), 1)
-        plan.run()
-        torch.cuda.synchronize()
-        worst = {}
-        for sc, dd in zip(scenes[::4], dev[::4]):
-            e = _sampled(sc.workload, dict(dd["grads"], rgb=dd["rgb"]), args.norm, n_sample=64)
-            for kk, vv in e.items():
-                worst[kk] = max(worst.get(kk, 0.0), vv)
-        res.update(value=round(evals / ms / 1e6, 4), ms_per_step=round(ms, 4), dtype="f32",
-                   config={"workload": f"{len(scenes)} scenes (N log-uniform in [5e4, 2e6], K in {{4,8,16}}, "
-                                       f"V in {{1,4,16}}), one persistent fused fwd+bwd launch, "
-                                       f"{args.norm} normaliser", "scenes": len(scenes),
-                           "primitives": sum(s.workload.n for s in scenes), "evals": evals,
-                           "tile_iters": ti, "blocks_per_cu": bpc, "work_items": plan.n_items},
-                   roofline=counters_roofline(f"nasg_batch_uneven{len(scenes)}_{args.norm}", ms, ab,
-                                              evals, alu=True),
-                   compare={"graph_replay": {"ms": round(ms_graph, 4),
-                                             "G_evals_s": round(evals / ms_graph / 1e6, 4)},
-                            "per_scene_launches": {"ms": round(ms_sep, 4),
-                                                   "G_evals_s": round(evals / ms_sep / 1e6, 4)},
-                            "tuner_sweep_ms": {f"tile{t_}_bpc{b_}": round(m_, 4) for m_, t_, b_ in sweep}},
-                   parity_sampled_max_scaled_error=worst)
     elif args.workload == "training-view":
         res.update(_training_view(args, log))
     else:
@@ -733,23 +881,14 @@ def main():
     evals = n * v
     value = evals / (ms * 1e-3) / 1e9
     abytes = algorithmic_bytes(n, k, v)
-    achieved = abytes / (ms * 1e-3) / 1e9
-    log(f"fused fwd+bwd {ms:.3f} ms/step, {value:.2f} G evals/s, {achieved:.0f} GB/s algorithmic")
-    counters = measured_counters(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}")
-    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes}
-    if counters is not None:
-        # VALU-issue roof: lane instructions per launch (SQ_INSTS_VALU x 64) over the live
-        # launch duration, against 256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz
-        lane_ops = counters["valu_wave_instructions_per_launch"] * 64
-        ach = lane_ops / (ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
-                    "unit": "T VALU lane-instructions/s", "frac": round(ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
-                    "traffic": counters["bytes_per_launch"],
-                    "lane_instructions_per_eval": round(lane_ops / (n * v), 1), "hbm": hbm,
-                    "kernel": "nasg_kernel (fused forward+backward)"}
-    else:
-        roofline = dict(hbm, bound="hbm", traffic=None, kernel="nasg_kernel (fused forward+backward)")
+    log(f"fused fwd+bwd {ms:.3f} ms/step, {value:.2f} G evals/s, "
+        f"{abytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+    ceiling, stream = None, None
+    if not args.quick:
+        stream, stream_sweep = stream_ceiling()
+        ceiling = stream["copy"]["GB_s"]
+        log(f"streaming ceiling: read {stream['read']['GB_s']} write {stream['write']['GB_s']} "
+            f"copy {stream['copy']['GB_s']} GB/s")
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "G evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -758,13 +897,15 @@ def main():
         "config": {"workload": f"NASGabor K={k} fused fwd+bwd, {n} primitives x {v} cameras, "
                                f"one launch, FP32 storage, {args.norm} normaliser",
                    "primitives": n, "lobes": k, "views": v, "norm": args.norm},
-        "roofline": roofline,
+        "roofline": roofline(f"nasg_fused_k{k}_v{v}_n{n}_{args.norm}", ms, abytes, evals,
+                             algorithmic_ops_per_eval(k, v, args.norm), ceiling=ceiling,
+                             kernel="nasg_kernel (fused forward+backward)"),
     }
 
     if not args.quick:
         cmp = {}
         steps = max(3, args.steps // 2)
-        # separate forward and backward launches
+
         def sep():
             P.nasg_eval_fwd(d["quat"], d["shape"], d["rgbw"], d["c0"], means=d["means"],
                             cams=d["cams"], norm=args.norm, out=rgb)
@@ -783,7 +924,6 @@ def main():
                                 cams=cams1[i], norm=args.norm, grads=g, accumulate=i > 0, rgb_out=rgb1)
         m = time_launches(single, max(2, steps // 4), 1)
         cmp["nasg_16_single_view_launches"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4)}
-        # the other normaliser
         other = "approx" if args.norm == "exact" else "exact"
 
         def fused_other():
@@ -793,14 +933,16 @@ def main():
         cmp[f"nasg_fused_{other}_normaliser"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4)}
         # SH degree 3, same means / cameras / upstream gradient
         gsh = {"sh": torch.empty_like(d["sh"]), "geom": torch.empty((n, 3), device="cuda")}
+        rsh = torch.empty_like(rgb)
 
         def sh():
             P.sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"], grads=gsh,
-                           rgb_out=rgb)
+                           rgb_out=rsh)
         m = time_launches(sh, steps, 1)
         sb = sh_bytes(n, v)
         cmp["sh3_fused"] = {"ms": round(m, 4), "G_evals_s": round(evals / m / 1e6, 4),
-                            "GB_s": round(sb / m / 1e6, 1), "hbm_frac": round(sb / m / 1e6 / HBM_PEAK_GBS, 4)}
+                            "roofline": roofline(f"sh3_fused_n{n}_v{v}", m, sb, evals, files=SH_SOURCES,
+                                                 ceiling=ceiling, kernel="sh3_kernel (fused)")}
         # plain FP32 single-view path on the same primitives (first camera)
         def plain():
             P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], gr1[0], means=d["means"],
@@ -810,18 +952,23 @@ def main():
         cmp["nasg_plain_single_view"] = {"ms": round(m, 4), "G_evals_s": round(n / m / 1e6, 4),
                                          "GB_s": round(pb / m / 1e6, 1),
                                          "hbm_frac": round(pb / m / 1e6 / HBM_PEAK_GBS, 4)}
-        cmp["hbm_copy_ceiling"] = copy_ceiling(steps)
-        hb = out["roofline"].get("hbm", out["roofline"])
-        hb["copy_ceiling_GB_s"] = cmp["hbm_copy_ceiling"]["GB_s"]
-        hb["frac_of_copy_ceiling"] = round(hb["achieved"] / cmp["hbm_copy_ceiling"]["GB_s"], 4)
-        out["compare"] = cmp
+        cmp["hbm_stream_ceiling"] = dict(stream, runtime_copy=copy_ceiling(steps), sweep_GB_s=stream_sweep)
         # sampled parity of the timed configuration (rerun the headline once)
         fused()
         torch.cuda.synchronize()
-        out["parity_sampled_max_scaled_error"] = sampled_parity(w, d, g, rgb, args.norm)
-        log(f"parity {out['parity_sampled_max_scaled_error']}")
-        del d, g, rgb, gsh
+        out["parity_sampled"] = _sampled(w, dict(g, rgb=rgb), args.norm, n_sample=512)
+        log(f"parity: worst scaled error {worst_scaled(out['parity_sampled']):.2e}")
+        del d, g, rgb, gsh, rsh, rgb1, cams1, gr1
         torch.cuda.empty_cache()
+        # the other workloads, each at its own full size in its benchmarked launch
+        cmp["single_camera_1M"] = measure_single_camera(args.norm, args.steps, args.warmup, log,
+                                                        ceiling=ceiling)
+        torch.cuda.empty_cache()
+        cmp["bf16_k16_6M_x8"] = measure_bf16_k16(args.norm, args.steps, args.warmup, log, ceiling=ceiling)
+        torch.cuda.empty_cache()
+        cmp["uneven_batch_32_scenes"] = measure_uneven_batch(args.norm, args.steps, args.warmup, log,
+                                                             ceiling=ceiling)
+        out["compare"] = cmp
         out["cpu_baseline"] = cpu_baseline(w, prims=args.cpu_prims,
                                            norm_code=0 if args.norm == "exact" else 1)
         log(f"cpu baseline {out['cpu_baseline']['value'] * 1e3:.3f} M evals/s")

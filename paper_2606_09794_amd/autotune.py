@@ -126,6 +126,65 @@ def tune(kernel: int, k: int, v: int, dtype: int, n: int, steps: int = 5, norm: 
     return choice
 
 
+# ---------------------------------------------------------------- batches
+# The persistent multi-scene launch has its own launch shape: the 256-thread
+# block passes per work item (tile size) and the persistent blocks per compute
+# unit. It is tuned on a whole batch and cached under the key "batch".
+BATCH_TILE_ITERS = (1, 2, 4, 8, 16)
+BATCH_BLOCKS_PER_CU = (1, 2, 3, 4)
+BATCH_FALLBACK = (4, 2)
+
+
+def batch_defaults(path: str = CACHE) -> Tuple[int, int]:
+    """(tile_iters, blocks_per_cu) from the cache's batch entry, else the
+    built-in (4, 2)."""
+    if os.path.exists(path):
+        with open(path) as fh:
+            ent = json.load(fh).get("batch")
+        if ent:
+            return int(ent["tile_iters"]), int(ent["blocks_per_cu"])
+    return BATCH_FALLBACK
+
+
+def tune_batch(scenes, norm: str = "exact", steps: int = 3, save: bool = True,
+               verbose: bool = True, path: str = CACHE) -> Dict:
+    """Time a persistent plan of `scenes` (the list NasgBatchPlan takes) for
+    every (tile_iters, blocks_per_cu) pair; the fastest is returned and, with
+    `save`, recorded as the cache's batch entry."""
+    import torch
+
+    from .api import NasgBatchPlan
+    results = []
+    for ti in BATCH_TILE_ITERS:
+        for bpc in BATCH_BLOCKS_PER_CU:
+            plan = NasgBatchPlan(scenes, norm=norm, tile_iters=ti, blocks_per_cu=bpc)
+            plan.run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                plan.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            results.append((ms, ti, bpc))
+            if verbose:
+                print(f"  batch tile_iters={ti} blocks_per_cu={bpc}: {ms:.3f} ms", flush=True)
+    ms, ti, bpc = min(results)
+    choice = {"tile_iters": ti, "blocks_per_cu": bpc, "ms": round(ms, 4), "scenes": len(scenes),
+              "sweep_ms": {f"tile{t_}_bpc{b_}": round(m_, 4) for m_, t_, b_ in results}}
+    if save:
+        data = {"arch": "gfx950", "entries": {}}
+        if os.path.exists(path):
+            with open(path) as fh:
+                data = json.load(fh)
+        data["batch"] = {k: v for k, v in choice.items() if k != "sweep_ms"}
+        with open(path + ".tmp", "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    return choice
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernels", default="nasg_fwd,nasg_bwd,sh_fwd,sh_bwd")
@@ -135,7 +194,26 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--cache", default=CACHE, help="JSON file the choices are written to")
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the persistent launch on the 32-scene uneven batch instead")
     args = ap.parse_args()
+    if args.batch:
+        import sys
+
+        import torch
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import workloads as W
+        from .api import nasg_grad_buffers as bufs
+        dev = []
+        for sc in W.config4():
+            w = sc.workload
+            t = {k: torch.from_numpy(getattr(w, k)).cuda()
+                 for k in ("quat", "shape", "rgbw", "c0", "means", "cams", "grad_rgb")}
+            t["grads"] = bufs(w.k, w.n, "cuda")
+            t["rgb"] = torch.empty((w.v, w.n, 3), device="cuda")
+            dev.append(t)
+        print(f"batch: {tune_batch(dev, path=args.cache)}", flush=True)
+        return
     for name in args.kernels.split(","):
         kern = KERNELS[name]
         for k in (args.k if kern < 2 else [0]):

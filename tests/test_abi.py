@@ -201,3 +201,21 @@ def test_raster_rejects(lib):
     assert bwd(gm=FAKE + 2) == -3
     assert bwd(gs=FAKE + 1) == -3
     assert bwd(gr=FAKE + 3) == -3
+
+
+def test_hbm_stream_rejects(lib):
+    s = lambda mode=2, src=FAKE, dst=FAKE + 4096, nb=4096, blocks=256, unroll=4, nt=0: \
+        lib.nasg_hbm_stream(mode, src, dst, nb, blocks, unroll, nt, None)  # noqa: E731
+    assert s(mode=3) == -5
+    assert s(mode=-1) == -5
+    assert s(nb=4095) == -2                 # not a multiple of 16 bytes
+    assert s(nb=-16) == -2
+    assert s(blocks=0) == -2
+    assert s(blocks=(1 << 20) + 1) == -2
+    assert s(unroll=3) == -2
+    assert s(nt=2) == -2
+    assert s(src=None) == -1
+    assert s(dst=None) == -1
+    assert s(mode=1, src=None, dst=FAKE + 8) == -3    # write: src unused, dst misaligned
+    assert s(src=FAKE + 4) == -3
+    assert s(nb=0) == 0                      # nothing to stream, nothing launched

@@ -59,31 +59,47 @@ def test_source_hash_ignores_comments_only():
     assert len(h) == 16 and h == bench.kernel_source_hash(bench.APPEARANCE_SOURCES)
 
 
-def test_committed_counters_match_their_sources():
-    """The counters bench.py prices the headline and compositing rooflines
-    with were taken on the kernel sources as committed (else bench.py falls
-    back to the HBM roofline with unknown traffic)."""
-    assert bench.measured_counters("nasg_fused_k8_v16_n3000000_exact") is not None
-    assert bench.measured_counters("raster_render_bwd_geom_n3000000_1920x1080",
-                                   bench.RASTER_SOURCES) is not None
-    for key in ("nasg_fused_k8_v1_n1048576_exact", "nasg_fused_k16_v8_n6000000_exact_bf16",
-                "nasg_fused_k8_v16_n3000000_exact_angles", "nasg_batch_uneven32_exact"):
-        assert bench.measured_counters(key) is not None, key
+def test_counters_are_used_only_on_their_sources(tmp_path, monkeypatch):
+    """Committed counters price a roofline only while the kernel sources they
+    were taken on are unchanged (comment edits aside); otherwise bench.py
+    reports the HBM roofline with unknown traffic."""
+    import json
+    h = bench.kernel_source_hash(bench.APPEARANCE_SOURCES)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    ent = {"source_hash": h, "bytes_per_launch": 3_500_000_000,
+           "valu_wave_instructions_per_launch": 1_000_000_000, "clock_GHz": 2.1}
+    (prof / "traffic.json").write_text(json.dumps({"cur": ent, "old": dict(ent, source_hash="0" * 16)}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda files=None: h)
+    assert bench.measured_counters("cur") is not None
+    assert bench.measured_counters("old") is None
+    assert bench.measured_counters("missing") is None
 
 
-def test_counters_roofline_bounds():
-    """The single-camera line stays on the HBM roof with its measured traffic;
-    the VALU-bound lines (bf16 K = 16, the persistent batch) report the issue
-    rate with the HBM figures beside; unknown counters give the HBM roof with
-    unknown traffic."""
-    ab = bench.algorithmic_bytes(1 << 20, 8, 1)
-    r = bench.counters_roofline("nasg_fused_k8_v1_n1048576_exact", 0.25, ab, 1 << 20, alu=False)
-    assert r["bound"] == "hbm" and r["traffic"] > ab and r["achieved"] == round(ab / 0.25 / 1e6, 1)
-    r = bench.counters_roofline("nasg_batch_uneven32_exact", 13.0, 25_156_165_456, 171_865_438, alu=True)
-    assert r["bound"] == "alu" and 0 < r["frac"] < 1 and r["hbm"]["algorithmic_bytes_per_launch"] > 0
-    assert r["profiled_launch"] == {"tile_iters": 8, "blocks_per_cu": 4}
-    r = bench.counters_roofline("no_such_key", 1.0, 1000, 10, alu=True)
+def test_roofline_object():
+    """frac is the algorithmic bytes against the 8 TB/s peak; the VALU issue
+    rate (from counters) and the algorithmic operation rate sit beside it;
+    unknown counters give unknown traffic."""
+    ab = bench.algorithmic_bytes(3_000_000, 8, 16)
+    ops = bench.algorithmic_ops_per_eval(8, 16)
+    r = bench.roofline("no_such_key", 2.0, ab, 48_000_000, ops, ceiling=5000.0)
     assert r["bound"] == "hbm" and r["traffic"] is None
+    assert r["achieved"] == round(ab / 2.0 / 1e6, 1) and r["frac"] == round(ab / 2.0 / 1e6 / 8000, 4)
+    assert r["bytes_per_eval"] == 71.0 and r["frac_of_stream_ceiling"] == round(ab / 2e6 / 5000, 4)
+    t = ops * 48_000_000 / 2e-3 / 1e12
+    assert r["algorithmic_ops"]["frac"] == round(t / 39.3216, 4)
+    assert "valu_issue" not in r and r["binding"] == "hbm"
+
+
+def test_algorithmic_ops_per_eval():
+    """Per primitive-view: K x 72 operations per lobe-view (26 value, 46
+    gradient), K x (frame 23 + normaliser 62 EXACT / 13 APPROX + write-out 41)
+    per lobe shared by the V views, 22 per view (direction, c0 and mean
+    gradients); counted from the formulas of the path."""
+    assert bench.algorithmic_ops_per_eval(8, 16, "exact") == 8 * 72 + 8 * 126 / 16 + 22 == 661
+    assert bench.algorithmic_ops_per_eval(8, 16, "approx") == 8 * 72 + 8 * 77 / 16 + 22
+    assert bench.algorithmic_ops_per_eval(8, 1, "exact") == 8 * 72 + 8 * 126 + 22
 
 
 @pytest.mark.parametrize("n", [2, 8])
