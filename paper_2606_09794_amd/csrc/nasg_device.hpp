@@ -170,9 +170,10 @@ __device__ inline void env_exp(double B, double& eb, double& em1) {
 
 // e^B and e^B - 1 for B <= 0: B = n ln2 + r, |r| <= ln2/2, e^r - 1 = r q(r)
 // with q the Taylor series of (e^r - 1)/r to r^9/10! (truncation ~3e-13).
-// e^B - 1 is formed as e^B - 1, an absolute error of ~1e-16, which is all its
-// uses need (it enters 2 lam (E kappa - 1) with lam <= ~1e3). B below -1400
-// is clamped (e^-1400 underflows FP64 to 0 either way).
+// For |B| <= ln2/2 (n = 0) e^B - 1 is the series value r q(r) itself, so it
+// keeps its relative accuracy however small B is; otherwise it is e^B - 1
+// (|e^B - 1| >= 0.29 there). B below -1400 is clamped (e^-1400 underflows FP64
+// to 0 either way).
 template <bool THREE_ADDR = false>
 __device__ inline void exp_em1(double B, double& eb, double& em1) {
   auto mad = [](double x, double y, double z) { return THREE_ADDR ? fma3(x, y, z) : fma(x, y, z); };
@@ -191,7 +192,7 @@ __device__ inline void exp_em1(double B, double& eb, double& em1) {
   q = mad(q, r, 0.5);
   q = fma(q, r, 1.0);
   eb = ldexp(fma(r, q, 1.0), static_cast<int>(n));
-  em1 = eb - 1.0;
+  em1 = n == 0.0 ? r * q : eb - 1.0;
 }
 
 // Nearest int of an integral double, saturated at the int range (the
@@ -317,66 +318,82 @@ struct LobeNorm {
   float dk, dz;   // d ln N / d k, d ln N / d zeta (zero for the NASG normaliser)
 };
 
-// e^{-L} S(r) and e^{-L} S'(r) with S(r) = sinh(sqrt r)/sqrt r continued to
-// r < 0 as sin(sqrt(-r))/sqrt(-r); r = L^2 - k^2 (Section 5.1, Psi). Power
-// series for |r| <= 1, otherwise the overflow-free exponential form with
-// s - L = -k^2 / (L + s).
-__device__ inline void exp_sinhc(double L, double k, double& F, double& dF) {
-  const double r = L * L - k * k;
-  double eL, unused;
-  if (fabs(r) <= 1.0) {
-    // 1/(2n+1)! for n = 0..13
-    constexpr double c[14] = {1.0,
-                              1.0 / 6.0,
-                              1.0 / 120.0,
-                              1.0 / 5040.0,
-                              1.0 / 362880.0,
-                              1.0 / 39916800.0,
-                              1.0 / 6227020800.0,
-                              1.0 / 1307674368000.0,
-                              1.0 / 355687428096000.0,
-                              1.0 / 121645100408832000.0,
-                              1.0 / 51090942171709440000.0,
-                              1.0 / 25852016738884976640000.0,
-                              1.0 / 15511210043330985984000000.0,
-                              1.0 / 10888869450418352160768000000.0};
-    double sr = c[13], ds = 13.0 * c[13];
-#pragma unroll
-    for (int n = 12; n >= 1; --n) {
-      sr = fma3(sr, r, c[n]);
-      ds = fma3(ds, r, n * c[n]);
-    }
-    sr = fma(sr, r, c[0]);
-    exp_em1<true>(-L, eL, unused);
-    F = eL * sr;
-    dF = eL * ds;
+// Psi(Lam, k) = 2 Lam e^{-Lam} S(r) / (1 - e^{-2 Lam}) of the closed-form
+// integral (Section 5.1), r = Lam^2 - k^2, S(r) = sinh(sqrt r)/sqrt r (continued
+// to r < 0 as sin(sqrt -r)/sqrt -r), and its partials in Lam and k.
+//
+// r > 1: with s = sqrt r and delta = Lam - s = k^2 / (Lam + s),
+//   Psi = (Lam/s) e^{-delta} (1 - e^{-2s}) / (1 - e^{-2 Lam}),
+//   d ln Psi/dLam = -k^2/(Lam s^2) + (delta/s)(1 + 2g) + 2 (g - g_Lam),
+//   d ln Psi/dk   = (k/s)(1/s - 1 - 2g),    g = e^{-2s}/(1 - e^{-2s}),
+//   g - g_Lam = -e^{-2s} expm1(-2 delta) / ((1 - e^{-2s})(1 - e^{-2 Lam})):
+//   every term vanishes with k instead of cancelling (Psi = 1 and both
+//   partials are 0 at k = 0), which keeps the partials relatively accurate
+//   where 1/(1 + cos(zeta) Psi) amplifies them (zeta near pi).
+// |r| <= 1: power series of S and S' (to r^9/19!); r < -1: sin t / t with
+//   t = sqrt(-r); then Psi and its partials from F = e^{-Lam} S and
+//   F' = e^{-Lam} S' directly (no small-k cancellation there: k is close to
+//   Lam or above it).
+// The two exponentials are shared by the branches: e^{-delta} or e^{-Lam},
+// and e^{-2s} or e^{-2 Lam}.
+__device__ inline void psi_partials(double L, double k, double iL, double& psi,
+                                    double& dpsi_dL, double& dpsi_dk) {
+  const double r = (L - k) * (L + k);
+  const bool hyp = r > 1.0;
+  const double ar = fmax(fabs(r), 1.0);
+  const double is = rsqrt64(ar);                   // 1/s, s = sqrt|r| (where |r| > 1)
+  const double s = ar * is;
+  const double delta = k * k * rcp64(L + s);
+  double e1, e1m1, e2, e2m1;
+  exp_em1<true>(hyp ? -delta : -L, e1, e1m1);      // e^{-delta} or e^{-Lam}
+  exp_em1<true>(hyp ? -2.0 * s : -2.0 * L, e2, e2m1);   // e^{-2s} or e^{-2 Lam}
+  if (hyp) {
+    const double Ds = -e2m1;                       // 1 - e^{-2s}
+    const double e2L = e2 * e1 * e1;               // e^{-2 Lam} = e^{-2s} e^{-2 delta}
+    const double DL = 1.0 - e2L;
+    const double iDD = rcp64(Ds * DL);
+    const double g = e2 * DL * iDD;
+    psi = L * is * e1 * Ds * Ds * iDD;
+    const double dlnL = fma(-k * k * iL, is * is, delta * is * fma(2.0, g, 1.0)) -
+                        2.0 * e2 * e1m1 * (2.0 + e1m1) * iDD;
+    const double dlnk = k * is * (is - 1.0 - 2.0 * g);
+    dpsi_dL = psi * dlnL;
+    dpsi_dk = psi * dlnk;
   } else {
-    // r > 1: sinh(a)/a with e^{-L} sinh(a) = (e^{a-L} - e^{-a-L})/2, a - L = -k^2/(L+a);
-    // r < -1: sin(a)/a. The square root, its reciprocal and the first exponential
-    // (e^{a-L} or e^{-L}) are shared by both cases.
-    const double a = sqrt64(fabs(r));
-    const double ia = rcp64(a);
-    const bool hyp = r > 0.0;
-    double ex;
-    exp_em1<true>(hyp ? -k * k * rcp64(L + a) : -L, ex, unused);
-    if (hyp) {
-      double em;
-      exp_em1<true>(-a - L, em, unused);
-      const double sh = 0.5 * (ex - em), ch = 0.5 * (ex + em);
-      F = sh * ia;
-      dF = (a * ch - sh) * 0.5 * ia * ia * ia;
+    double F, dF;
+    if (!(fabs(r) > 1.0)) {
+      // 1/(2n+1)! for n = 0..9
+      constexpr double c[10] = {1.0, 1.0 / 6.0, 1.0 / 120.0, 1.0 / 5040.0, 1.0 / 362880.0,
+                                1.0 / 39916800.0, 1.0 / 6227020800.0, 1.0 / 1307674368000.0,
+                                1.0 / 355687428096000.0, 1.0 / 121645100408832000.0};
+      double sr = c[9], ds = 9.0 * c[9];
+#pragma unroll
+      for (int n = 8; n >= 1; --n) {
+        sr = fma3(sr, r, c[n]);
+        ds = fma3(ds, r, n * c[n]);
+      }
+      sr = fma(sr, r, c[0]);
+      F = e1 * sr;
+      dF = e1 * ds;
     } else {
       double sn, cs;
-      sincos_turns(a * kInvTwoPi, sn, cs);
-      F = ex * sn * ia;
-      dF = ex * (sn - a * cs) * 0.5 * ia * ia * ia;
+      sincos_turns(s * kInvTwoPi, sn, cs);
+      F = e1 * sn * is;
+      dF = e1 * fma(-s, cs, sn) * 0.5 * is * is * is;
     }
+    const double iD = rcp64(-e2m1);                // 1 / (1 - e^{-2 Lam})
+    psi = 2.0 * L * F * iD;
+    const double dF_dL = fma(2.0 * L, dF, -F);
+    dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) * iD - 4.0 * L * F * e2 * iD * iD;
+    dpsi_dk = -4.0 * L * k * dF * iD;
   }
 }
 
 // Normaliser of one lobe and the log-derivatives the backward pass needs.
 // mode 0: 1 / closed-form integral (Section 5.1; the phase multiplies Psi by
-//         cos zeta);
+//         cos zeta): I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) B,
+//         B = 1 + cos(zeta) Psi, which FP64 keeps relatively accurate down to
+//         B ~ 1e-9 (zeta within ~5e-5 of pi with Psi -> 1);
 // mode 1: NASG normaliser lambda sqrt(1+a) / (2 pi (1 - e^{-2 lambda})).
 __device__ inline LobeNorm lobe_norm(double lam, double a, double kd, double zd, int mode) {
   double e2l, em1_2l;
@@ -384,9 +401,11 @@ __device__ inline LobeNorm lobe_norm(double lam, double a, double kd, double zd,
   const double dlam = -em1_2l;                    // 1 - e^{-2 lam}, relatively accurate
   const double sq = sqrt64(1.0 + a);
   const double idl = rcp64(dlam);
+  const double il = rcp64(lam);
+  const double ia = rcp64(1.0 + a);
   // d/dlam ln(lam / (1 - e^{-2 lam})) = 1/lam - 2 e^{-2 lam} / (1 - e^{-2 lam})
-  const double dl_base = rcp64(lam) - 2.0 * e2l * idl;
-  const double da_base = 0.5 * rcp64(1.0 + a);
+  const double dl_base = il - 2.0 * e2l * idl;
+  const double da_base = 0.5 * ia;
   LobeNorm out;
   if (mode == 1) {
     out.n = static_cast<float>(lam * sq * idl * (0.5 / kPi));
@@ -396,26 +415,18 @@ __device__ inline LobeNorm lobe_norm(double lam, double a, double kd, double zd,
     out.dz = 0.f;
     return out;
   }
-  const double k = kd;
   const double L = lam * (1.0 + a);
-  double F, dFs;
-  exp_sinhc(L, k, F, dFs);
-  double e2L, em1_2L;
-  exp_em1<true>(-2.0 * L, e2L, em1_2L);
-  const double iD = rcp64(-em1_2L);               // 1 / (1 - e^{-2L})
-  const double psi = 2.0 * L * F * iD;
-  const double dF_dL = -F + 2.0 * L * dFs;
-  const double dpsi_dL = (2.0 * F + 2.0 * L * dF_dL) * iD - 4.0 * L * F * e2L * iD * iD;
-  const double dpsi_dk = -4.0 * L * k * dFs * iD;
+  double psi, dpsi_dL, dpsi_dk;
+  psi_partials(L, kd, il * ia, psi, dpsi_dL, dpsi_dk);
   double sz, cz;
   sincos_turns(zd * kInvTwoPi, sz, cz);
-  const double B = 1.0 + cz * psi;
+  const double B = fma(cz, psi, 1.0);
   const double iB = rcp64(B);
-  // I = pi (1 - e^{-2 lam}) / (lam sqrt(1+a)) * B ;  N = 1/I
+  const double czB = cz * iB;
   out.n = static_cast<float>(lam * sq * idl * iB * (1.0 / kPi));
-  out.dl = static_cast<float>(dl_base - cz * dpsi_dL * (1.0 + a) * iB);
-  out.da = static_cast<float>(da_base - cz * dpsi_dL * lam * iB);
-  out.dk = static_cast<float>(-cz * dpsi_dk * iB);
+  out.dl = static_cast<float>(dl_base - czB * dpsi_dL * (1.0 + a));
+  out.da = static_cast<float>(da_base - czB * dpsi_dL * lam);
+  out.dk = static_cast<float>(-czB * dpsi_dk);
   out.dz = static_cast<float>(sz * psi * iB);
   return out;
 }

@@ -14,8 +14,9 @@
 // leave its lane and a view's sums travel with its slot: no cross-lane
 // reduction per lobe, no atomics, a fixed summation order.
 //
-// Numerics: the view direction, the frame axes and the dot products d.x, d.z,
-// h = 1 - d.z and 1 - (d.z)^2 = h (2 - h) are FP64 (the lobes reach
+// Numerics: the view direction, the frame axes, d.x, the squared chord
+// |d + z|^2 = 4 kappa (relatively accurate next to the antipode, where
+// 1 + d.z would cancel), h = 1 - d.z and 1 - (d.z)^2 are FP64 (the lobes reach
 // lambda (1 + a) ~ 1e6, where FP32 rounding of d.z alone moves G by ~1e-4);
 // the carrier phase is reduced in FP64 to its offset from the nearest peak or
 // zero, which keeps the carrier and its derivative relatively accurate at its
@@ -35,6 +36,8 @@
 //   dG/dx   = s_x d,  s_x = G (2 lam E kappa + 1) L 2 a d.x/(1-(d.z)^2) + k N p E dc/dtheta
 //   dG/dz   = s_z d,  s_z = G [lam (1+tau) E + tau/(2 kappa)
 //                             + (2 lam E kappa + 1) L tau 2 d.z/(1-(d.z)^2)]
+//                         = G [(2 lam E kappa + 1) tau Q + lam E],
+//                       Q = 1/(2 kappa) + 2 d.z L/(1-(d.z)^2)  (formed in FP64)
 //   dG/dd   = s_x x + s_z z.
 #include <hip/hip_runtime.h>
 
@@ -148,16 +151,26 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           // d = -z (kappa = 0) G and every gradient are forced to 0 and kappa is
           // kept away from 0 where it is inverted.
           const double dxd = sl.dd[t][0] * xa0 + sl.dd[t][1] * xa1 + sl.dd[t][2] * xa2;
-          const double dzd = sl.dd[t][0] * za0 + sl.dd[t][1] * za1 + sl.dd[t][2] * za2;
-          const double hd = 1.0 - dzd;
-          const double opd = 1.0 + dzd;             // 2 kappa
-          const bool live = opd > 0.0;
-          // 2 kappa kept below 2 - 2^-52 (so kappa -> 1 stays in the top
-          // ln-table bucket); kappa = lm 2^(le - 1). The table entry is fetched
-          // first, its use comes after the carrier and 1/(1 - (d.z)^2).
-          const double opc = fmin(opd, 0x1.fffffffffffffp0);
+          // q = |d + z|^2 = 2 (1 + d.z) = 4 kappa from the chord: relatively
+          // accurate next to the antipode, where 1 + d.z would cancel. Every
+          // other quantity derives from q: kappa = q/4 (exact), h = 1 - d.z =
+          // 2 - q/2 (exact where q >= 2, Sterbenz), so kappa and h are
+          // consistent and the table ln needs no correction for kappa's own
+          // rounding. Next to the axis h keeps an absolute error ~2e-16;
+          // nothing below is sensitive to h's relative error there (G, s_x
+          // and a's gradient depend on tau only through tau ln kappa and ln
+          // kappa/(1 - (d.z)^2), s_z through tau Q, all smooth in h).
+          const double e0 = sl.dd[t][0] + za0;
+          const double e1 = sl.dd[t][1] + za1;
+          const double e2 = sl.dd[t][2] + za2;
+          const double q = fma(e0, e0, fma(e1, e1, e2 * e2));
+          const double hd = fma(q, -0.5, 2.0);
+          const double opd = 0.5 * q;                // 2 kappa
+          const bool live = q > 0.0;
+          // kappa = lm 2^(le - 2). The table entry is fetched first, its use
+          // comes after the carrier and 1/(1 - (d.z)^2).
           int le;
-          const double lm = frexp(opc, &le);
+          const double lm = frexp(q, &le);
           const LogEntry lt = ltab[log_bucket(lm)];
           __builtin_amdgcn_sched_barrier(0);   // keep the table read ahead of the carrier work
           const double dend = hd * opd;              // 1 - (d.z)^2
@@ -187,9 +200,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double ud = dxd * dxd * rden;        // tau / a
           const double taud = and_ * ud;
           __builtin_amdgcn_sched_barrier(0);
-          // near kappa = 1 (1 + d.z in [1, 2)) the exact kappa is 1 - h/2 and
-          // ((1 + d.z) - 2 + h)/2 is the rounding error of the computed one
-          const double Ld = log_finish(lm, le - 1, lt, 0.5 * ((opc - 2.0) + hd));
+          const double Ld = log_finish(lm, le - 2, lt, 0.0);
           const double Ad = taud * Ld;               // ln E
           double Ekd, em1d;
           env_exp(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
@@ -202,6 +213,10 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           if constexpr (BWD) {
             const float L = static_cast<float>(Ld);
             const float LR = pole ? -0.25f : static_cast<float>(Ld * rden);  // ln kappa/(1-(d.z)^2)
+            // Q = 1/(2 kappa) + 2 d.z ln kappa/(1 - (d.z)^2) = (h + 2 d.z ln kappa)/(1 - (d.z)^2)
+            // in FP64: its two terms (each ~1/2) cancel next to the axis, where
+            // Q -> 3h/8 (0 at d = z, where rden is 0)
+            const float Q = static_cast<float>(fma(q - 2.0, Ld, hd) * rden);   // 2 d.z = q - 2
             const float u = static_cast<float>(ud);
             const float tau = static_cast<float>(taud);
             const float em1 = static_cast<float>(em1d);
@@ -225,8 +240,8 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             const float GTLR = G * T2 * LR;
             const float sx = fmaf(GTLR, two_an * dx, Sth * kf);
             const float inv2k = __builtin_amdgcn_rcpf(opf);   // 1/(2 kappa)
-            const float sz = fmaf(GTLR * tau, 2.f * static_cast<float>(dzd),
-                                  G * inv2k * fmaf(fmaf(two_lam, tau, two_lam), Ek, tau));
+            // s_z = G [(2 lam E kappa + 1) tau Q + lam E], lam E = 2 lam E kappa / (2 kappa)
+            const float sz = G * fmaf(T2 * tau, Q, two_lam * Ek * inv2k);
             const float gsx = gG * sx, gsz = gG * sz;
             ax0 = fmaf(gsx, sl.df[t][0], ax0);
             ax1 = fmaf(gsx, sl.df[t][1], ax1);
