@@ -368,6 +368,27 @@ int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
                     float* grad_colors, float* grad_opac, float* grad_means,
                     float* grad_scales, float* grad_rots, void* stream);
 
+/* ---- compositing forward without allocation --------------------------------
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid it): nasg_raster_fwd with its
+ * workspace taken from a fixed device array inside the library instead of a
+ * caller buffer. Same inputs, image and kernels as nasg_raster_fwd; the
+ * overflow flag, which nasg_raster_fwd leaves at workspace byte 0, is copied
+ * to `overflow` (a device int32, nullable). The array holds
+ * NASG_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU the library runs on, from the
+ * first call on that GPU until the process ends; a forward whose workspace
+ * (nasg_raster_workspace_bytes) exceeds it returns NASG_ERR_WORKSPACE and
+ * launches nothing. Nothing is allocated, freed or synchronised. Every call
+ * on one GPU uses that GPU's array and leaves its state there (each call
+ * clears what must start at zero), so calls that overlap on one GPU (other
+ * streams, other threads) race; a backward cannot follow this forward (use
+ * nasg_raster_fwd with a caller workspace for training).                    */
+#define NASG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int nasg_raster_fwd_noalloc(const nasg_gaussians* g, const nasg_camera* cam,
+                            int32_t tile_capacity, float* image, int32_t* overflow,
+                            void* stream);
+
 /* ---- achievable HBM rate (measurement) -------------------------------------
  * Streams `bytes` (a multiple of 16) through HBM with plain 16-byte accesses:
  * NASG_STREAM_READ reads src (dst: at least 16 bytes, written only in a case

@@ -19,6 +19,7 @@ PARAM_QUAT, PARAM_ANGLES = 0, 1
 FAMILIES = {"nasgabor": 0, "nasg": 1, "sg": 2, "sb": 3, "sc": 4, "asg": 5}
 KERNEL_NASG_FWD, KERNEL_NASG_BWD, KERNEL_SH_FWD, KERNEL_SH_BWD = 0, 1, 2, 3
 STREAM_READ, STREAM_WRITE, STREAM_COPY = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class NasgParams(C.Structure):
@@ -89,6 +90,8 @@ EXPORTS = {
     "nasg_raster_bwd": (C.c_int, [C.POINTER(NasgGaussians), C.POINTER(NasgCamera), C.c_int32,
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "nasg_raster_fwd_noalloc": (C.c_int, [C.POINTER(NasgGaussians), C.POINTER(NasgCamera),
+                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "nasg_hbm_stream": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_void_p]),
     "nasg_status_string": (C.c_char_p, [C.c_int]),

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -218,6 +219,43 @@ int raster_args(const nasg_gaussians* g, const nasg_camera* cam, int32_t cap, co
   a->pix_state = reinterpret_cast<double*>(base + L.image_off);
   a->grad_acc = reinterpret_cast<double*>(base + L.acc_off);
   return NASG_OK;
+}
+
+}  // namespace
+
+// ---- compositing forward without allocation
+// The workspace of nasg_raster_fwd_noalloc: a file-scope device array, one per
+// GPU the library runs on, held until the process ends. In host code its name
+// is only a stand-in; the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[NASG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+
+ScratchSlot& scratch_slot(int dev) {
+  static ScratchSlot slots[kMaxScratchDevices];
+  return slots[dev];
+}
+
+// Device address of this GPU's scratch array (the current device's).
+void* device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+  ScratchSlot& sl = scratch_slot(dev);
+  std::call_once(sl.once, [&sl] {
+    void* p = nullptr;
+    sl.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    sl.ptr = sl.err == hipSuccess ? p : nullptr;
+  });
+  return sl.ptr;
 }
 
 }  // namespace
@@ -489,6 +527,33 @@ int nasg_raster_fwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t til
   return nasg::launch_raster(a, false, static_cast<hipStream_t>(stream)) == hipSuccess
              ? NASG_OK
              : NASG_ERR_LAUNCH;
+}
+
+int nasg_raster_fwd_noalloc(const nasg_gaussians* g, const nasg_camera* cam,
+                            int32_t tile_capacity, float* image, int32_t* overflow,
+                            void* stream) {
+  if (g == nullptr || cam == nullptr) return NASG_ERR_NULL;
+  RasterLayout L{};
+  if (!raster_layout(g->n, cam, tile_capacity, &L)) return NASG_ERR_SHAPE;
+  if (L.total > static_cast<size_t>(NASG_NOALLOC_SCRATCH_BYTES)) return NASG_ERR_WORKSPACE;
+  if (image == nullptr) return NASG_ERR_NULL;
+  if (!aligned(image, 4) || (overflow && !aligned(overflow, 4))) return NASG_ERR_ALIGN;
+  // every argument is validated before the runtime is touched: the first
+  // raster_args only checks and lays out (at a stand-in aligned address)
+  nasg::RasterArgs a{};
+  int st = raster_args(g, cam, tile_capacity, reinterpret_cast<const void*>(uintptr_t{256}),
+                       NASG_NOALLOC_SCRATCH_BYTES, &a);
+  if (st != NASG_OK) return st;
+  void* ws = device_scratch();
+  if (ws == nullptr) return NASG_ERR_LAUNCH;
+  st = raster_args(g, cam, tile_capacity, ws, NASG_NOALLOC_SCRATCH_BYTES, &a);
+  if (st != NASG_OK) return st;
+  a.image_out = image;
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (nasg::launch_raster(a, false, hs) != hipSuccess) return NASG_ERR_LAUNCH;
+  if (overflow != nullptr && nasg::launch_copy_flag(a.overflow, overflow, hs) != hipSuccess)
+    return NASG_ERR_LAUNCH;
+  return NASG_OK;
 }
 
 int nasg_raster_bwd(const nasg_gaussians* g, const nasg_camera* cam, int32_t tile_capacity,

@@ -78,4 +78,7 @@ struct RasterArgs {
 
 hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s);
 
+// One-thread copy of a device int32 (the overflow flag out of a workspace).
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s);
+
 }  // namespace nasg

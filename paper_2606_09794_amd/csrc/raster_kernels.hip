@@ -1022,6 +1022,13 @@ __global__ __launch_bounds__(256 / RPL) void raster_render_bwd(RasterArgs a) {
   }
 }
 
+__global__ void raster_copy_flag(const int32_t* src, int32_t* dst) { *dst = *src; }
+
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(raster_copy_flag, dim3(1), dim3(1), 0, s, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_raster(const RasterArgs& a, bool bwd, hipStream_t s) {
   const int64_t n_tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
   const unsigned gt = static_cast<unsigned>((n_tiles + 255) / 256);

@@ -219,3 +219,27 @@ def test_hbm_stream_rejects(lib):
     assert s(mode=1, src=None, dst=FAKE + 8) == -3    # write: src unused, dst misaligned
     assert s(src=FAKE + 4) == -3
     assert s(nb=0) == 0                      # nothing to stream, nothing launched
+
+
+def test_raster_fwd_noalloc_rejects(lib):
+    """Invalid arguments, and a workspace beyond the fixed scratch, are refused
+    on the host before the runtime is touched."""
+    cam = L.NasgCamera((C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1), (C.c_double * 3)(0, 0, 0),
+                       100.0, 100.0, 32.0, 24.0, 64, 48)
+    g = L.NasgGaussians(FAKE, FAKE, FAKE, FAKE, FAKE, 10)
+    f = lambda gg=C.byref(g), cc=C.byref(cam), cap=256, img=FAKE, ov=None: \
+        lib.nasg_raster_fwd_noalloc(gg, cc, cap, img, ov, None)  # noqa: E731
+    assert f(gg=None) == -1
+    assert f(cc=None) == -1
+    assert f(cap=0) == -2
+    assert f(img=None) == -1
+    assert f(img=FAKE + 2) == -3
+    assert f(ov=FAKE + 1) == -3
+    g.opac = None
+    assert f() == -1
+    g.opac = FAKE
+    # 1920 x 1080 at capacity 4096 needs 0.27 GB of lists alone: beyond the 64 MiB
+    big = L.NasgCamera(cam.rot, cam.t, 1000.0, 1000.0, 960.0, 540.0, 1920, 1080)
+    need = lib.nasg_raster_workspace_bytes(10, C.byref(big), 4096)
+    assert need > L.NOALLOC_SCRATCH_BYTES
+    assert f(cc=C.byref(big), cap=4096) == -7
