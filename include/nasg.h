@@ -410,12 +410,19 @@ const char* nasg_status_string(int status);
 
 /* ---- launch tuning --------------------------------------------------------
  * The evaluators map each primitive to `lanes` consecutive lanes of a
- * wavefront (1, 2, 4, 8 or 16), each lane holding `views_per_lane` views at a
- * time; V larger than lanes * views_per_lane is processed in chunks of that
- * many views, accumulated in place, so any pair accepted below serves any V.
- * The accepted (lanes, views_per_lane) pairs are (1, 1), (1, 2), (1, 4),
- * (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2) and
- * (16, 1); others return NASG_ERR_SHAPE. nasg_set_tuning overrides the built-in
+ * wavefront (1, 2, 4, 8 or 16); lane j owns lobes j, j + lanes, ... With
+ * bcast = 0 the views travel: each lane holds `views_per_lane` views of a
+ * chunk of lanes * views_per_lane and passes them round the group, so every
+ * lobe meets every view. With bcast = 1 every lane holds the same
+ * `views_per_lane` views (a chunk of that many) and the per-view colour and
+ * direction-gradient sums are reduced over the group afterwards: for few
+ * views, it spreads a primitive's lobes over the lanes. V larger than a chunk
+ * is processed in chunks, accumulated in place, so any accepted mapping
+ * serves any V. Accepted (lanes, views_per_lane): bcast = 0: (1, 1), (1, 2),
+ * (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2),
+ * (16, 1); bcast = 1 (NASGabor kernels 0 and 1 only): (4, 1), (8, 1),
+ * (16, 1), (8, 2), (8, 4); others return NASG_ERR_SHAPE. nasg_set_tuning
+ * overrides the built-in
  * choice for a (kernel, K, V, dtype) key; nasg_get_tuning reports the choice
  * that a call with that key would use. kernel: 0 = NASG forward, 1 = NASG
  * backward / fused, 2 = SH forward, 3 = SH backward. K is ignored for SH.
@@ -427,6 +434,7 @@ typedef struct nasg_tuning {
   int32_t block;       /* threads per block: 64, 128 or 256 (the kernels are
                           compiled for at most 256; other values return
                           NASG_ERR_SHAPE)                                     */
+  int32_t bcast;       /* 0: travelling views, 1: broadcast views (above)     */
 } nasg_tuning;
 
 int nasg_set_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype,

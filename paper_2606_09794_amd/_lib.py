@@ -54,7 +54,8 @@ class NasgBatch(C.Structure):
 
 
 class NasgTuning(C.Structure):
-    _fields_ = [("lanes", C.c_int32), ("views_per_lane", C.c_int32), ("block", C.c_int32)]
+    _fields_ = [("lanes", C.c_int32), ("views_per_lane", C.c_int32), ("block", C.c_int32),
+                ("bcast", C.c_int32)]
 
 
 class NasgCamera(C.Structure):

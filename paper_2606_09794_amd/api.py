@@ -273,15 +273,16 @@ class NasgBatchPlan:
 
 
 def set_tuning(kernel: int, k: int, v: int, dtype: int, lanes: int, views_per_lane: int,
-               block: int = 256) -> None:
-    t = L.NasgTuning(lanes, views_per_lane, block)
+               block: int = 256, bcast: int = 0) -> None:
+    t = L.NasgTuning(lanes, views_per_lane, block, bcast)
     L.check(L.lib().nasg_set_tuning(kernel, k, v, dtype, C.byref(t)), "nasg_set_tuning")
 
 
 def get_tuning(kernel: int, k: int, v: int, dtype: int):
+    """(lanes, views_per_lane, block, bcast) a call with this key would use."""
     t = L.NasgTuning()
     L.check(L.lib().nasg_get_tuning(kernel, k, v, dtype, C.byref(t)), "nasg_get_tuning")
-    return (t.lanes, t.views_per_lane, t.block)
+    return (t.lanes, t.views_per_lane, t.block, t.bcast)
 
 
 # ------------------------------------------------------------------ autograd

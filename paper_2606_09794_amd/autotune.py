@@ -22,6 +22,8 @@ from .api import (get_tuning, nasg_eval_bwd, nasg_eval_fwd, nasg_grad_buffers, s
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 MAPPINGS: List[Tuple[int, int]] = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2),
                                    (4, 4), (8, 1), (8, 2), (16, 1)]
+# the broadcast-view mappings (NASGabor kernels only)
+BCAST_MAPPINGS: List[Tuple[int, int]] = [(4, 1), (8, 1), (16, 1), (8, 2), (8, 4)]
 BLOCKS = (64, 128, 256)
 KERNELS = {"nasg_fwd": L.KERNEL_NASG_FWD, "nasg_bwd": L.KERNEL_NASG_BWD,
            "sh_fwd": L.KERNEL_SH_FWD, "sh_bwd": L.KERNEL_SH_BWD}
@@ -40,7 +42,8 @@ def load_cache(path: str = CACHE) -> int:
     count = 0
     for key, ent in data.get("entries", {}).items():
         kernel, k, v, dtype = (int(x) for x in key.split("/"))
-        set_tuning(kernel, k, v, dtype, ent["lanes"], ent["views_per_lane"], ent["block"])
+        set_tuning(kernel, k, v, dtype, ent["lanes"], ent["views_per_lane"], ent["block"],
+                   ent.get("bcast", 0))
         count += 1
     return count
 
@@ -99,11 +102,15 @@ def tune(kernel: int, k: int, v: int, dtype: int, n: int, steps: int = 5, norm: 
             sh3_eval_bwd(d["sh"], d["grad_rgb"], means=d["means"], cams=d["cams"], grads=gsh, rgb_out=out)
 
     results = []
-    for lanes, vpl in MAPPINGS:
-        if lanes > max(1, v) or lanes * vpl > 4 * max(v, 1):
-            continue
+    cands = [(lanes, vpl, 0) for lanes, vpl in MAPPINGS
+             if lanes <= max(1, v) and lanes * vpl <= 4 * max(v, 1)]
+    if kernel in (L.KERNEL_NASG_FWD, L.KERNEL_NASG_BWD):
+        # broadcast views: lanes up to the lobe count, views per lane up to V
+        cands += [(lanes, vpl, 1) for lanes, vpl in BCAST_MAPPINGS
+                  if lanes <= max(4, k) and vpl <= max(1, v)]
+    for lanes, vpl, bc in cands:
         for block in BLOCKS:
-            set_tuning(kernel, k, v, dtype, lanes, vpl, block)
+            set_tuning(kernel, k, v, dtype, lanes, vpl, block, bc)
             call()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -113,16 +120,17 @@ def tune(kernel: int, k: int, v: int, dtype: int, n: int, steps: int = 5, norm: 
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            results.append((ms, lanes, vpl, block))
+            results.append((ms, lanes, vpl, block, bc))
             if verbose:
                 print(f"  kernel={kernel} K={k} V={v} dtype={dtype} lanes={lanes} vpl={vpl} "
-                      f"block={block}: {ms:.3f} ms", flush=True)
-    ms, lanes, vpl, block = min(results)
-    set_tuning(kernel, k, v, dtype, lanes, vpl, block)
-    choice = {"lanes": lanes, "views_per_lane": vpl, "block": block, "ms": round(ms, 4), "n": n}
+                      f"bcast={bc} block={block}: {ms:.3f} ms", flush=True)
+    ms, lanes, vpl, block, bc = min(results)
+    set_tuning(kernel, k, v, dtype, lanes, vpl, block, bc)
+    choice = {"lanes": lanes, "views_per_lane": vpl, "block": block, "bcast": bc,
+              "ms": round(ms, 4), "n": n}
     if save:
         save_entry(kernel, k, v, dtype, choice, path=cache)
-    assert get_tuning(kernel, k, v, dtype) == (lanes, vpl, block)
+    assert get_tuning(kernel, k, v, dtype) == (lanes, vpl, block, bc)
     return choice
 
 

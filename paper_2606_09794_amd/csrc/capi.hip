@@ -35,7 +35,15 @@ std::map<Key, nasg_tuning>& tuning_table() {
   return t;
 }
 
-bool supported(int lanes, int vpl) {
+bool supported(int lanes, int vpl, int bcast) {
+  if (bcast == 1) {
+#define NASG_OK_BC(P_, V_) \
+    if (lanes == P_ && vpl == V_) return true;
+    NASG_FOR_EACH_BCAST_CONFIG(NASG_OK_BC)
+#undef NASG_OK_BC
+    return false;
+  }
+  if (bcast != 0) return false;
 #define NASG_OK_CASE(P_, V_) \
   if (lanes == P_ && vpl == V_) return true;
   NASG_FOR_EACH_CONFIG(NASG_OK_CASE)
@@ -49,11 +57,11 @@ bool block_ok(int b) { return b == 64 || b == 128 || b == 256; }
 // views per lane, so per-view state stays within the registers of two waves
 // per SIMD, and the lane group (<= one DPP row) covers up to 16 views.
 nasg_tuning heuristic(int32_t v) {
-  if (v <= 1) return {1, 1, 256};
-  if (v == 2) return {1, 2, 256};
-  if (v <= 4) return {2, 2, 256};
-  if (v <= 8) return {4, 2, 256};
-  return {8, 2, 256};
+  if (v <= 1) return {1, 1, 256, 0};
+  if (v == 2) return {1, 2, 256, 0};
+  if (v <= 4) return {2, 2, 256, 0};
+  if (v <= 8) return {4, 2, 256, 0};
+  return {8, 2, 256, 0};
 }
 
 nasg_tuning choose(int32_t kernel, int32_t k, int32_t v, int32_t dtype) {
@@ -284,7 +292,9 @@ int nasg_set_tuning(int32_t kernel, int32_t k, int32_t v, int32_t dtype, const n
     tuning_table().erase(key);
     return NASG_OK;
   }
-  if (!supported(t->lanes, t->views_per_lane) || !block_ok(t->block)) return NASG_ERR_SHAPE;
+  if (!supported(t->lanes, t->views_per_lane, t->bcast) || !block_ok(t->block) ||
+      (kernel >= 2 && t->bcast != 0))
+    return NASG_ERR_SHAPE;
   tuning_table()[key] = *t;
   return NASG_OK;
 }
@@ -309,7 +319,7 @@ int nasg_eval_fwd(const nasg_params* p, const nasg_views* views, float* rgb, int
   a.rgb = rgb;
   a.norm = norm;
   const nasg_tuning t = choose(0, p->k, views->v, p->dtype);
-  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, false,
+  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, t.bcast != 0, false,
                                          p->dtype == NASG_BF16, t.block,
                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;
@@ -337,7 +347,7 @@ int nasg_eval_bwd(const nasg_params* p, const nasg_views* views, const float* gr
   a.norm = norm;
   a.accumulate = grad_mode == NASG_GRAD_ACCUMULATE;
   const nasg_tuning t = choose(1, p->k, views->v, p->dtype);
-  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, true,
+  const hipError_t e = nasg::launch_nasg(a, t.lanes, t.views_per_lane, t.bcast != 0, true,
                                          p->dtype == NASG_BF16, t.block,
                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NASG_OK : NASG_ERR_LAUNCH;

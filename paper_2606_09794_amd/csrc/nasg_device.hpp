@@ -133,9 +133,29 @@ constexpr int kLogEntries = 1 << kLogBits;
 __device__ inline int log_bucket(double m) {
   return (__double2hiint(m) >> (20 - kLogBits)) & (kLogEntries - 1);
 }
-__device__ inline double log_finish(double m, int e, const LogEntry& t, double dkap) {
+// A constant held in a vector register the compiler cannot see through, so
+// that a polynomial step with two constant operands (a coefficient times the
+// variable plus a coefficient) still encodes as one fused multiply-add: the
+// hardware takes at most one scalar operand besides literals, and without it
+// the compiler copies the second constant into a register before every use.
+__device__ __forceinline__ double vreg_const(double c) {
+  double r;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(c));
+  return r;
+}
+
+// a * b + c with b a scalar operand (the one the encoding allows besides
+// vector registers), so that no copy of c is made.
+__device__ __forceinline__ double fma_vsv(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+  return d;
+}
+
+__device__ inline double log_finish(double m, int e, const LogEntry& t, double dkap,
+                                    double third = 1.0 / 3.0) {
   const double r = fma(m, t.inv_c, -1.0) - dkap;
-  double p = fma(r, -0.25, 1.0 / 3.0);
+  double p = fma_vsv(r, -0.25, third);
   p = fma(p, r, -0.5);
   const double lp = fma(p, r * r, r);
   return fma(static_cast<double>(e), kLn2, t.ln_c + lp);
@@ -152,12 +172,12 @@ __device__ inline double log_kappa(double kap, double dkap, const LogEntry* tab)
 // (relative truncation r^8/9! <= 6e-10 at |r| = ln2/2, far smaller near
 // B = 0 where 2 lam (e^B - 1) is large). e^B - 1 is formed as e^B - 1, an
 // absolute error ~1e-16. B below -1e6 is clamped (e^B is 0 there).
-__device__ inline void env_exp(double B, double& eb, double& em1) {
+__device__ inline void env_exp(double B, double& eb, double& em1,
+                               double inv8f = 1.0 / 40320.0) {
   B = fmax(B, -1.0e6);
   const double n = rint(B * kLog2e);
   const double r = fma(-n, kLn2, B);
-  double q = 1.0 / 40320.0;            // 1/8!
-  q = fma(q, r, 1.0 / 5040.0);
+  double q = fma(inv8f, r, 1.0 / 5040.0);   // 1/8! r + 1/7!
   q = fma(q, r, 1.0 / 720.0);
   q = fma(q, r, 1.0 / 120.0);
   q = fma(q, r, 1.0 / 24.0);
@@ -215,11 +235,11 @@ __device__ inline float exp_neg(double X) {
   return ldexpf(p, sat_int(n));
 }
 
-// sin(pi x) and cos(pi x) in FP32 for |x| <= 1/4: Taylor series of sine to
-// y^9 and cosine to y^10 in y = pi x, |y| <= pi/4 (truncation below 2e-8
+// sin(pi x/2) and cos(pi x/2) in FP32 for |x| <= 1/2: Taylor series of sine
+// to y^9 and cosine to y^10 in y = pi x/2, |y| <= pi/4 (truncation below 2e-8
 // relative).
-__device__ inline void sincospi_quarter(float x, float& s, float& c) {
-  const float y = 3.14159265358979323846f * x;
+__device__ inline void sincos_halfpi(float x, float& s, float& c) {
+  const float y = 1.57079632679489661923f * x;
   const float z = y * y;
   float ps = 1.f / 362880.f;
   ps = fmaf(ps, z, -1.f / 5040.f);

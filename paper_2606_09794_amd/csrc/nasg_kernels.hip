@@ -45,13 +45,23 @@
 #include "nasg_launch.hpp"
 #include "nasg_skeleton.hpp"
 
+#ifndef NASG_BC_WAVES
+#define NASG_BC_WAVES 3
+#endif
+
 namespace nasg {
 
 // One primitive-lane-group's work: primitive `prim` (may be >= n for tail
 // lanes, which compute on a real primitive and write nothing), lane j of P.
 // NOCAR: the NASG lobe (Supplementary E): no carrier (k = zeta = 0) and the
 // NASG normaliser, which is exact for it.
-template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR = false>
+// BC (views broadcast): the P lanes of a primitive own its lobes as usual but
+// every lane holds the same VPL views, so each lane evaluates its lobes
+// against all of them with no slot transfer, and the per-view colour and
+// direction-gradient partials are summed over the lane group at the end (DPP).
+// For few views this spreads a primitive over P lanes (P lobes prepared and
+// loaded at once) instead of one lane walking all of them.
+template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR = false, bool BC = false>
 __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j,
                                           const LogEntry* ltab) {
   using S = Store<BF16>;
@@ -61,16 +71,18 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
   const int V = a.v;
   const int K = a.k;
   const int rot_addr = group_next_addr<P>();
+  const double k_third = vreg_const(1.0 / 3.0);
+  const double k_inv8f = vreg_const(1.0 / 40320.0);
 
   const float c0v[3] = {a.c0[3 * i + 0], a.c0[3 * i + 1], a.c0[3 * i + 2]};
   const float* bp = a.dirs != nullptr ? a.dirs : a.means;
   const double base[3] = {bp[3 * i + 0], bp[3 * i + 1], bp[3 * i + 2]};
 
-  for (int v0 = 0; v0 < V; v0 += P * VPL) {
+  for (int v0 = 0; v0 < V; v0 += BC ? VPL : P * VPL) {
     // gradients of later view chunks accumulate onto the first chunk's
     const bool acc_mode = a.accumulate || v0 > 0;
     ViewSlots<VPL> sl;
-    slots_setup<P, VPL, BWD>(a, i, v0, j, base, c0v, sl);
+    slots_setup<P, VPL, BWD, BC>(a, i, v0, j, base, c0v, sl);
 
     // ---- lobes, P at a time: lane j owns lobe lc + j. The view slots travel
     // round the lane group (lane j takes over the slot of lane j + 1 after
@@ -143,7 +155,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       float ax0 = 0.f, ax1 = 0.f, ax2 = 0.f, az0 = 0.f, az1 = 0.f, az2 = 0.f;
 
 #pragma unroll 2
-      for (int step = 0; step < P; ++step) {
+      for (int step = 0; step < (BC ? 1 : P); ++step) {
 #pragma unroll
         for (int t = 0; t < VPL; ++t) {
           // Branch-free. A view slot beyond V carries a real direction and a zero
@@ -188,7 +200,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             const double th = fma(dxd, kh, zh);
             const double nh = rint(th);
             float sa, ca;
-            sincospi_quarter(0.5f * static_cast<float>(th - nh), sa, ca);
+            sincos_halfpi(static_cast<float>(th - nh), sa, ca);
             peak = (static_cast<int>(nh) & 1) == 0;
             const float cpk = peak ? ca : sa;
             car = cpk * cpk;
@@ -200,10 +212,10 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           const double ud = dxd * dxd * rden;        // tau / a
           const double taud = and_ * ud;
           __builtin_amdgcn_sched_barrier(0);
-          const double Ld = log_finish(lm, le - 2, lt, 0.0);
+          const double Ld = log_finish(lm, le - 2, lt, 0.0, k_third);
           const double Ad = taud * Ld;               // ln E
           double Ekd, em1d;
-          env_exp(Ad + Ld, Ekd, em1d);               // E kappa and E kappa - 1
+          env_exp(Ad + Ld, Ekd, em1d, k_inv8f);      // E kappa and E kappa - 1
           const float pE = exp_neg(fma(two_lamd, em1d, Ad));
           const float Npe = live ? Nn * pE : 0.f;
           const float G = Npe * car;
@@ -211,13 +223,11 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           sl.col[t][1] = fmaf(w1, G, sl.col[t][1]);
           sl.col[t][2] = fmaf(w2, G, sl.col[t][2]);
           if constexpr (BWD) {
-            const float L = static_cast<float>(Ld);
             const float LR = pole ? -0.25f : static_cast<float>(Ld * rden);  // ln kappa/(1-(d.z)^2)
             // Q = 1/(2 kappa) + 2 d.z ln kappa/(1 - (d.z)^2) = (h + 2 d.z ln kappa)/(1 - (d.z)^2)
             // in FP64: its two terms (each ~1/2) cancel next to the axis, where
             // Q -> 3h/8 (0 at d = z, where rden is 0)
             const float Q = static_cast<float>(fma(q - 2.0, Ld, hd) * rden);   // 2 d.z = q - 2
-            const float u = static_cast<float>(ud);
             const float tau = static_cast<float>(taud);
             const float em1 = static_cast<float>(em1d);
             const float g0 = sl.gr[t][0], g1 = sl.gr[t][1], g2 = sl.gr[t][2];
@@ -232,7 +242,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             // the FP32 difference would carry its absolute error into E kappa
             const float Ek = static_cast<float>(Ekd);
             const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
-            acc_a = fmaf(qG * T2 * L, u, acc_a);
+            acc_a = fmaf(qG * T2 * LR, dx * dx, acc_a);   // ln kappa tau/a = LR (d.x)^2
             const float Sth = (peak ? -scp : scp) * Npe;      // N p E dc/dtheta
             const float gS = gG * Sth;
             acc_k = fmaf(gS, dx, acc_k);
@@ -255,7 +265,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           }
           // pass this view slot on (this lane takes the slot of lane j + 1) as
           // soon as it is done, so the transfer overlaps the next view's work
-          if constexpr (P > 1) {
+          if constexpr (P > 1 && !BC) {
             slot_pass<P, VPL, BWD>(sl, t, rot_addr);
             __builtin_amdgcn_sched_barrier(0);
           }
@@ -284,20 +294,21 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       }
     }
 
-    slots_finish<P, VPL, BWD>(a, i, valid, v0, j, acc_mode, sl);
+    slots_finish<P, VPL, BWD, BC>(a, i, valid, v0, j, acc_mode, sl);
   }
 }
 
-template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
 // One lane and one view per primitive run three waves per SIMD (the few spills
-// land in the once-per-lobe preparation); the other mappings keep two, where the
-// full register budget pays more than a third wave.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 && VPL == 1 ? 3 : 2)))
+// land in the once-per-lobe preparation), and so do broadcast views; the other
+// mappings keep two, where the full register budget pays more than a third wave.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    BC ? NASG_BC_WAVES : (P == 1 && VPL == 1 ? 3 : 2))))
 void nasg_kernel(const NasgArgs a) {
   __shared__ LogEntry ltab[kLogEntries];
   load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  nasg_body<P, VPL, BWD, BF16, ANG, NOCAR>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
+  nasg_body<P, VPL, BWD, BF16, ANG, NOCAR, BC>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
 }
 
 // ------------------------------------------------------- persistent batch
@@ -396,31 +407,31 @@ hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, cons
 
 // ------------------------------------------------------------ instantiation
 
-template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
 static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
   const int64_t threads = a.n * P;
   const int64_t grid = (threads + block - 1) / block;
-  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR>),
+  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC>),
                      dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
-template <int P, int VPL, bool ANG, bool NOCAR>
+template <int P, int VPL, bool ANG, bool NOCAR, bool BC>
 static hipError_t launch_pa(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s) {
-  if (bwd) return bf16 ? launch_one<P, VPL, true, true, ANG, NOCAR>(a, block, s)
-                       : launch_one<P, VPL, true, false, ANG, NOCAR>(a, block, s);
-  return bf16 ? launch_one<P, VPL, false, true, ANG, NOCAR>(a, block, s)
-              : launch_one<P, VPL, false, false, ANG, NOCAR>(a, block, s);
+  if (bwd) return bf16 ? launch_one<P, VPL, true, true, ANG, NOCAR, BC>(a, block, s)
+                       : launch_one<P, VPL, true, false, ANG, NOCAR, BC>(a, block, s);
+  return bf16 ? launch_one<P, VPL, false, true, ANG, NOCAR, BC>(a, block, s)
+              : launch_one<P, VPL, false, false, ANG, NOCAR, BC>(a, block, s);
 }
 
-template <int P, int VPL, bool NOCAR>
+template <int P, int VPL, bool NOCAR, bool BC = false>
 static hipError_t launch_pv(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s) {
-  return a.param == kParamAngles ? launch_pa<P, VPL, true, NOCAR>(a, bwd, bf16, block, s)
-                                 : launch_pa<P, VPL, false, NOCAR>(a, bwd, bf16, block, s);
+  return a.param == kParamAngles ? launch_pa<P, VPL, true, NOCAR, BC>(a, bwd, bf16, block, s)
+                                 : launch_pa<P, VPL, false, NOCAR, BC>(a, bwd, bf16, block, s);
 }
 
-hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
-                       hipStream_t s) {
+hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bcast, bool bwd, bool bf16,
+                       int block, hipStream_t s) {
   if (a.family == kFamNasg) {
     // NASG lobes: the compiled family mappings, chosen by view count
     int fl, fv;
@@ -433,6 +444,13 @@ hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf1
     }
   }
   if (a.family != kFamNasgabor) return launch_family(a, bwd, bf16, block, s);
+  if (bcast) {
+#define NASG_BC_CASE(P_, V_) \
+    if (lanes == P_ && vpl == V_) return launch_pv<P_, V_, false, true>(a, bwd, bf16, block, s);
+    NASG_FOR_EACH_BCAST_CONFIG(NASG_BC_CASE)
+#undef NASG_BC_CASE
+    return hipErrorInvalidValue;
+  }
 #define NASG_CASE(P_, V_) \
   if (lanes == P_ && vpl == V_) return launch_pv<P_, V_, false>(a, bwd, bf16, block, s);
   NASG_FOR_EACH_CONFIG(NASG_CASE)

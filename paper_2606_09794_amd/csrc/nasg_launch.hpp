@@ -79,6 +79,16 @@ struct ShArgs {
   X(8, 2)                       \
   X(16, 1)
 
+// (lanes per primitive, views per lane) pairs compiled with the views
+// broadcast to every lane of the group (lanes own lobes, per-view sums reduced
+// over the group): the mappings for few views.
+#define NASG_FOR_EACH_BCAST_CONFIG(X) \
+  X(4, 1)                             \
+  X(8, 1)                             \
+  X(16, 1)                            \
+  X(8, 2)                             \
+  X(8, 4)
+
 // Persistent multi-scene launch: device-side plan layout (in the caller's
 // workspace): BatchHeader | BatchScene[n_scenes] | BatchItem[n_items].
 struct BatchHeader {
@@ -111,8 +121,8 @@ hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, cons
 // SG, SB, SC and ASG lobes (csrc/family_kernels.hip), lane mapping by view count.
 hipError_t launch_family(const NasgArgs& a, bool bwd, bool bf16, int block, hipStream_t s);
 
-hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bwd, bool bf16, int block,
-                       hipStream_t s);
+hipError_t launch_nasg(const NasgArgs& a, int lanes, int vpl, bool bcast, bool bwd, bool bf16,
+                       int block, hipStream_t s);
 hipError_t launch_sh(const ShArgs& a, int lanes, int vpl, bool bwd, int block, hipStream_t s);
 
 }  // namespace nasg

@@ -96,8 +96,11 @@ struct ViewSlots {
   bool has[VPL];          // the view exists (v < V)
 };
 
-// Fills this lane's home slot of the view chunk starting at v0.
-template <int P, int VPL, bool BWD>
+// Fills this lane's home slot of the view chunk starting at v0. BC (views
+// broadcast): every lane of the group holds the same views v0 + t, t < VPL,
+// and only lane 0's colours start from c0 (the group's partial colours are
+// summed after the lobes).
+template <int P, int VPL, bool BWD, bool BC = false>
 __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0, int j,
                                             const double (&base)[3], const float (&c0)[3],
                                             ViewSlots<VPL>& s) {
@@ -105,7 +108,7 @@ __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0
   const int V = a.v;
 #pragma unroll
   for (int t = 0; t < VPL; ++t) {
-    const int v = v0 + j + P * t;
+    const int v = BC ? v0 + t : v0 + j + P * t;
     s.has[t] = v < V;
     double e0 = base[0], e1 = base[1], e2 = base[2];
     if (a.dirs == nullptr) {
@@ -122,9 +125,10 @@ __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0
     s.df[t][1] = static_cast<float>(s.dd[t][1]);
     s.df[t][2] = static_cast<float>(s.dd[t][2]);
     s.rinv[t] = static_cast<float>(ri);
-    s.col[t][0] = c0[0];
-    s.col[t][1] = c0[1];
-    s.col[t][2] = c0[2];
+    const bool own_c0 = !BC || j == 0;
+    s.col[t][0] = own_c0 ? c0[0] : 0.f;
+    s.col[t][1] = own_c0 ? c0[1] : 0.f;
+    s.col[t][2] = own_c0 ? c0[2] : 0.f;
     s.gdir[t][0] = s.gdir[t][1] = s.gdir[t][2] = 0.f;
     if constexpr (BWD) {
       if (s.has[t]) {
@@ -158,16 +162,29 @@ __device__ __forceinline__ void slot_pass(ViewSlots<VPL>& s, int t, int rot_addr
 
 // With the slots home again: the colours of this lane's views, and the c0 and
 // mean (or dirs) gradients of the primitive (sums over its views, reduced
-// over the lane group, written by lane 0).
-template <int P, int VPL, bool BWD>
+// over the lane group, written by lane 0). BC: the group's partial colours
+// and direction gradients are first summed over its lanes (each lane then
+// holds the totals of all VPL views); lane t % P writes view t's colour, and
+// the c0 and mean gradients are not summed over lanes again.
+template <int P, int VPL, bool BWD, bool BC = false>
 __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool valid, int v0,
-                                             int j, bool acc_mode, const ViewSlots<VPL>& s) {
+                                             int j, bool acc_mode, ViewSlots<VPL>& s) {
   const int64_t N = a.n;
+  if constexpr (BC) {
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s.col[t][c] = group_sum<P>(s.col[t][c]);
+        if constexpr (BWD) s.gdir[t][c] = group_sum<P>(s.gdir[t][c]);
+      }
+    }
+  }
   if (a.rgb != nullptr && valid) {
 #pragma unroll
     for (int t = 0; t < VPL; ++t) {
-      if (!s.has[t]) continue;
-      const int64_t o = (static_cast<int64_t>(v0 + j + P * t) * N + i) * 3;
+      if (!s.has[t] || (BC && j != t % P)) continue;
+      const int64_t o = (static_cast<int64_t>(BC ? v0 + t : v0 + j + P * t) * N + i) * 3;
       a.rgb[o + 0] = s.col[t][0];
       a.rgb[o + 1] = s.col[t][1];
       a.rgb[o + 2] = s.col[t][2];
@@ -187,12 +204,14 @@ __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool 
       gm1 = fmaf(s.gdir[t][1] - pr * s.df[t][1], s.rinv[t], gm1);
       gm2 = fmaf(s.gdir[t][2] - pr * s.df[t][2], s.rinv[t], gm2);
     }
-    gc0 = group_sum<P>(gc0);
-    gc1 = group_sum<P>(gc1);
-    gc2 = group_sum<P>(gc2);
-    gm0 = group_sum<P>(gm0);
-    gm1 = group_sum<P>(gm1);
-    gm2 = group_sum<P>(gm2);
+    if constexpr (!BC) {
+      gc0 = group_sum<P>(gc0);
+      gc1 = group_sum<P>(gc1);
+      gc2 = group_sum<P>(gc2);
+      gm0 = group_sum<P>(gm0);
+      gm1 = group_sum<P>(gm1);
+      gm2 = group_sum<P>(gm2);
+    }
     if (valid && j == 0) {
       if (a.g_c0 != nullptr) {
         float* dst = a.g_c0 + 3 * i;
