@@ -53,15 +53,15 @@ bool supported(int lanes, int vpl, int bcast) {
 
 bool block_ok(int b) { return b == 64 || b == 128 || b == 256; }
 
-// Built-in choice when no tuning entry exists (measured on MI355X): up to two
-// views per lane, so per-view state stays within the registers of two waves
-// per SIMD, and the lane group (<= one DPP row) covers up to 16 views.
+// Built-in choice when no tuning entry exists (the tuner's picks at K = 8 on
+// MI355X): one lane per primitive up to four views (no slot transfers), then
+// four lanes with two or four views each, so that a lane evaluates several
+// independent lobe-views per step within the registers of two waves per SIMD.
 nasg_tuning heuristic(int32_t v) {
   if (v <= 1) return {1, 1, 256, 0};
-  if (v == 2) return {1, 2, 256, 0};
-  if (v <= 4) return {2, 2, 256, 0};
-  if (v <= 8) return {4, 2, 256, 0};
-  return {8, 2, 256, 0};
+  if (v <= 4) return {1, 4, 256, 0};
+  if (v <= 8) return {4, 2, 128, 0};
+  return {4, 4, 128, 0};
 }
 
 nasg_tuning choose(int32_t kernel, int32_t k, int32_t v, int32_t dtype) {

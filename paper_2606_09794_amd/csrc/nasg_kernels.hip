@@ -373,17 +373,17 @@ void nasg_batched_kernel(const BatchHeader* hdr,
     if constexpr (RAW) {
       switch (sc.variant) {
         case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 1: batch_tile<1, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 2: batch_tile<4, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
         case 3: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 4: batch_tile<2, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-        default: batch_tile<8, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 4: batch_tile<1, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+        default: batch_tile<4, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
       }
     } else {
       switch (sc.variant) {
         case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 1: batch_tile<2, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 2: batch_tile<8, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 1: batch_tile<1, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+        case 2: batch_tile<4, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
         default: break;
       }
     }

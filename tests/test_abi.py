@@ -119,7 +119,7 @@ def test_status_strings_and_tuning(lib):
     assert (out.lanes, out.views_per_lane, out.block) == (4, 2, 128)
     assert lib.nasg_set_tuning(1, 8, 16, 0, C.byref(L.NasgTuning(0, 0, 0))) == 0
     assert lib.nasg_get_tuning(1, 8, 16, 0, C.byref(out)) == 0
-    assert (out.lanes, out.views_per_lane) == (8, 2)           # built-in choice for V = 16
+    assert (out.lanes, out.views_per_lane) == (4, 4)           # built-in choice for V = 16
     assert lib.nasg_set_tuning(9, 8, 16, 0, C.byref(t)) == -5
 
 
@@ -153,10 +153,10 @@ def test_batched_rejects(lib):
     bad = L.NasgBatch(FAKE, 0, 5, 1, 1, 0, 1, 2)                # raw-values flag neither 0 nor 1
     assert lib.nasg_batched_run(C.byref(bad), None) == -7
     assert C.sizeof(L.NasgBatch) == 48                          # the C layout of nasg_batch
-    # the work list grows with the tile count: at V = 2 a primitive has 2 lanes, so
-    # one tile is 4 passes x 128 primitives
+    # the work list grows with the tile count: at V = 2 a primitive has one lane,
+    # so one tile is 4 passes x 256 primitives
     sc[0].grad_rgb = FAKE
-    sc[0].p.n = 512 * 3 + 1
+    sc[0].p.n = 1024 * 3 + 1
     assert lib.nasg_batched_workspace_bytes(sc, 1, C.byref(t)) == need + 3 * 16
 
 
