@@ -451,4 +451,179 @@ __device__ inline LobeNorm lobe_norm(double lam, double a, double kd, double zd,
   return out;
 }
 
+
+// ------------------------------------------------ normaliser, FP32 fast path
+// The same normaliser and log-derivatives in FP32 for lam >= 1/2 and
+// Lam = lam (1 + a) >= 3/2, the range every lobe of a trained model or a
+// log-uniform draw in [1, 1e3] falls in; smaller lam or Lam take the FP64
+// code above. In that range nothing below cancels by more than a factor of a
+// few, so FP32 keeps N relatively accurate to ~1e-6 and the log-derivatives
+// to ~1e-6 of their size:
+// - 1 - e^{-2 lam} >= 0.63 and d/dlam ln(lam / (1 - e^{-2 lam})) >= 0.84;
+// - B = 1 + cos(zeta) Psi is formed as (1 - Psi) + Psi (1 + cos zeta), with
+//   sin zeta, cos zeta and 1 + cos zeta each relatively accurate (the phase
+//   is reduced in FP64): for 0 <= Psi <= 1 two terms of one sign, for Psi < 0
+//   (|Psi| < 0.22) B >= 0.78, so B keeps its relative accuracy as zeta -> pi
+//   and k -> 0 drive it to 0, and the k and zeta log-derivatives keep theirs
+//   next to the zeros of cos zeta and sin zeta;
+// - where Lam^2 - k^2 > 1, with s, delta, g as in psi_partials and
+//   m = 1 - e^{-delta} (relatively accurate),
+//     1 - Psi = [m (1 + e^{-delta} e^{-2s}) - delta e^{-delta} (1 - e^{-2s})/s]
+//               / (1 - e^{-2 Lam}),
+//   whose two terms (~delta and ~delta/s) differ by at least a factor s >= 3/2
+//   for small k, and the log-derivatives are those of psi_partials with
+//   1 - e^{-2 delta} = m (2 - m): every term vanishes with k;
+// - elsewhere (|Lam^2 - k^2| <= 1, or k^2 > Lam^2 + 1) k >= 1.1, Psi <= 0.83,
+//   and Psi and its partials come from e^{-Lam} S(r) and e^{-Lam} S'(r) as in
+//   psi_partials: S and S' by their series to r^6/13! (both positive there),
+//   or, where k^2 > Lam^2 + 1, sin t / t and its derivative in FP64, since
+//   they cross zero and the k and zeta gradients scale with them.
+
+__device__ inline float exp_f(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// e^x - 1 for x <= 0, relatively accurate: the Taylor series to x^8/8! for
+// x > -1/2 (truncation below 1e-8 relative), e^x - 1 below (|e^x - 1| >= 0.39).
+__device__ inline float expm1_neg_f(float x) {
+  float p = 1.f / 40320.f;
+  p = fmaf(p, x, 1.f / 5040.f);
+  p = fmaf(p, x, 1.f / 720.f);
+  p = fmaf(p, x, 1.f / 120.f);
+  p = fmaf(p, x, 1.f / 24.f);
+  p = fmaf(p, x, 1.f / 6.f);
+  p = fmaf(p, x, 0.5f);
+  p = fmaf(p, x, 1.f);
+  return x > -0.5f ? p * x : exp_f(x) - 1.f;
+}
+
+// sin, cos and 1 + cos of (pi/2) x for x given in FP64: x is split into its
+// nearest integer n (the quadrant) and the exact offset |g| <= 1/2, so all
+// three stay relatively accurate next to their zeros (1 + cos near x = 2 is
+// formed as 1 - cos(pi g/2) from the cosine series itself).
+__device__ inline void sincos_phase(double x, float& s, float& c, float& opc) {
+  const double n = rint(x);
+  const float y = 1.57079632679489661923f * static_cast<float>(x - n);
+  const float z = y * y;
+  float ps = 1.f / 362880.f;
+  ps = fmaf(ps, z, -1.f / 5040.f);
+  ps = fmaf(ps, z, 1.f / 120.f);
+  ps = fmaf(ps, z, -1.f / 6.f);
+  const float sy = fmaf(y * z, ps, y);
+  float pc = -1.f / 3628800.f;
+  pc = fmaf(pc, z, 1.f / 40320.f);
+  pc = fmaf(pc, z, -1.f / 720.f);
+  pc = fmaf(pc, z, 1.f / 24.f);
+  pc = fmaf(pc, z, -0.5f);
+  const float omc = -z * pc;                           // 1 - cos y
+  const float cy = 1.f - omc;
+  const int q = sat_int(n) & 3;
+  s = (q == 0) ? sy : (q == 1) ? cy : (q == 2) ? -sy : -cy;
+  c = (q == 0) ? cy : (q == 1) ? -sy : (q == 2) ? -cy : sy;
+  opc = (q == 2) ? omc : 1.f + c;
+}
+
+// zh = zeta / pi in FP64 (the carrier's own phase offset); lam, a, k as the
+// caller holds them (FP64 for the paper's activated values), rounded to FP32
+// here except where the sine branch needs them exact.
+__device__ inline LobeNorm lobe_norm_f32(double lamd, double ad, double kd, double zh, int mode) {
+  const float lam = static_cast<float>(lamd), a = static_cast<float>(ad), k = static_cast<float>(kd);
+  const float e2l = exp_f(-2.f * lam);
+  const float idl = __builtin_amdgcn_rcpf(1.f - e2l);
+  const float il = __builtin_amdgcn_rcpf(lam);
+  const float opa = 1.f + a;
+  const float ia = __builtin_amdgcn_rcpf(opa);
+  const float sq = opa * __builtin_amdgcn_rsqf(opa);
+  const float dl_base = il - 2.f * e2l * idl;
+  const float da_base = 0.5f * ia;
+  LobeNorm out;
+  if (mode == 1) {
+    out.n = lam * sq * idl * static_cast<float>(0.5 / kPi);
+    out.dl = dl_base;
+    out.da = da_base;
+    out.dk = 0.f;
+    out.dz = 0.f;
+    return out;
+  }
+  const float L = lam * opa;
+  const float r = (L - k) * (L + k);
+  const bool hyp = r > 1.f;
+  const float ar = fmaxf(fabsf(r), 1.f);
+  const float is = __builtin_amdgcn_rsqf(ar);          // 1/s
+  const float s = ar * is;
+  const float delta = k * k * __builtin_amdgcn_rcpf(L + s);
+  const float e1 = exp_f(hyp ? -delta : -L);           // e^{-delta} or e^{-Lam}
+  const float e2 = exp_f(hyp ? -2.f * s : -2.f * L);   // e^{-2s} or e^{-2 Lam}
+  float psi, om, dPL, dPk;
+  if (hyp) {
+    const float Ds = 1.f - e2;
+    const float iDs = __builtin_amdgcn_rcpf(Ds);
+    const float iDL = __builtin_amdgcn_rcpf(1.f - e2 * e1 * e1);
+    const float g = e2 * iDs;
+    psi = L * is * e1 * Ds * iDL;
+    const float m = -expm1_neg_f(-delta);              // 1 - e^{-delta}
+    om = (m * fmaf(e1, e2, 1.f) - delta * e1 * Ds * is) * iDL;
+    const float dlnL = fmaf(-k * k * il * ia, is * is, delta * is * fmaf(2.f, g, 1.f)) +
+                       2.f * e2 * (m * (2.f - m)) * iDL * iDs;
+    const float dlnk = k * is * (is - 1.f - 2.f * g);
+    dPL = psi * dlnL;
+    dPk = psi * dlnk;
+  } else {
+    float S, dS;
+    if (!(fabsf(r) > 1.f)) {
+      // S(r) = sum r^n/(2n+1)! and S'(r), n <= 6
+      S = 1.f / 6227020800.f;
+      dS = 6.f / 6227020800.f;
+      S = fmaf(S, r, 1.f / 39916800.f);
+      dS = fmaf(dS, r, 5.f / 39916800.f);
+      S = fmaf(S, r, 1.f / 362880.f);
+      dS = fmaf(dS, r, 4.f / 362880.f);
+      S = fmaf(S, r, 1.f / 5040.f);
+      dS = fmaf(dS, r, 3.f / 5040.f);
+      S = fmaf(S, r, 1.f / 120.f);
+      dS = fmaf(dS, r, 2.f / 120.f);
+      S = fmaf(S, r, 1.f / 6.f);
+      dS = fmaf(dS, r, 1.f / 6.f);
+      S = fmaf(S, r, 1.f);
+    } else {
+      // sin t / t and its derivative in r, t = sqrt(k^2 - Lam^2), in FP64:
+      // S'(r) = (sin t - t cos t)/(2 t^3) and S itself cross zero, and both
+      // must stay relatively accurate there (the k and zeta gradients scale
+      // with them); FP32 rounding of t alone would move them by ~1e-6 t
+      const double Ld = lamd * (1.0 + ad);
+      const double t2 = (kd - Ld) * (kd + Ld);
+      const double it = rsqrt64(t2);
+      const double t = t2 * it;
+      double sn, cs;
+      sincos_turns(t * kInvTwoPi, sn, cs);
+      S = static_cast<float>(sn * it);
+      dS = static_cast<float>(fma(-t, cs, sn) * (0.5 * it * it * it));
+    }
+    const float F = e1 * S;
+    const float dF = e1 * dS;
+    const float iD = __builtin_amdgcn_rcpf(1.f - e2);
+    psi = 2.f * L * F * iD;
+    om = 1.f - psi;
+    const float dF_dL = fmaf(2.f * L, dF, -F);
+    dPL = fmaf(2.f, F, 2.f * L * dF_dL) * iD - 4.f * L * F * e2 * iD * iD;
+    dPk = -4.f * L * k * dF * iD;
+  }
+  float sz, cz, opc;
+  sincos_phase(2.0 * zh, sz, cz, opc);                 // sin, cos and 1 + cos of zeta
+  const float B = fmaf(psi, opc, om);
+  const float iB = __builtin_amdgcn_rcpf(B);
+  const float czB = cz * iB;
+  out.n = lam * sq * idl * iB * static_cast<float>(1.0 / kPi);
+  out.dl = dl_base - czB * dPL * opa;
+  out.da = da_base - czB * dPL * lam;
+  out.dk = -czB * dPk;
+  out.dz = sz * psi * iB;
+  return out;
+}
+
+// The normaliser by the FP32 path where it applies, by the FP64 one elsewhere.
+__device__ inline LobeNorm lobe_norm_any(double lam, double a, double kd, double zd, int mode) {
+  const float lf = static_cast<float>(lam), af = static_cast<float>(a);
+  if (lf >= 0.5f && lf * (1.f + af) >= 1.5f) return lobe_norm_f32(lam, a, kd, zd * kInvPi, mode);
+  return lobe_norm(lam, a, kd, zd, mode);
+}
+
 }  // namespace nasg

@@ -137,7 +137,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       const double zd = NOCAR ? 0.0 : static_cast<double>(sh.w);
       const double kh = kd * kInvPi;
       const double zh = zd * kInvPi;
-      const LobeNorm nm = lobe_norm(lamd, ad, kd, zd, NOCAR ? 1 : a.norm);
+      const LobeNorm nm = lobe_norm_any(lamd, ad, kd, zd, NOCAR ? 1 : a.norm);
       const float Nn = own ? nm.n : 0.f;
       const float kf = static_cast<float>(kd);
       const float two_lam = static_cast<float>(2.0 * lamd);
