@@ -619,11 +619,19 @@ __device__ inline LobeNorm lobe_norm_f32(double lamd, double ad, double kd, doub
   return out;
 }
 
+// The FP64 normaliser as a called function: it runs only for the rare lobes
+// outside the FP32 range, and kept out of line its FP64 temporaries do not
+// count against the calling kernel's register budget.
+__device__ __noinline__ LobeNorm lobe_norm_outlined(double lam, double a, double kd, double zd,
+                                                    int mode) {
+  return lobe_norm(lam, a, kd, zd, mode);
+}
+
 // The normaliser by the FP32 path where it applies, by the FP64 one elsewhere.
 __device__ inline LobeNorm lobe_norm_any(double lam, double a, double kd, double zd, int mode) {
   const float lf = static_cast<float>(lam), af = static_cast<float>(a);
   if (lf >= 0.5f && lf * (1.f + af) >= 1.5f) return lobe_norm_f32(lam, a, kd, zd * kInvPi, mode);
-  return lobe_norm(lam, a, kd, zd, mode);
+  return lobe_norm_outlined(lam, a, kd, zd, mode);
 }
 
 }  // namespace nasg

@@ -91,15 +91,32 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
     // stay in the lane that owns it; a view's colour and direction gradient
     // travel with its slot. A lane with no lobe left (K not a multiple of P)
     // carries a zero normaliser and adds nothing.
+    auto load_rec = [&](int lc_, float4& q_, float4& sh_, float& w0_, float& w1_, float& w2_) {
+      const int lo_ = lc_ + j < K ? lc_ + j : K - 1;
+      const int64_t oi_ = static_cast<int64_t>(lo_) * N + i;
+      q_ = S::load4(a.quat, oi_);
+      sh_ = S::load4(a.shape, oi_);
+      w0_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 0) * N + i);
+      w1_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 1) * N + i);
+      w2_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 2) * N + i);
+    };
+    // Where a lane meets several views per lobe, the next lobe group's
+    // records are loaded while the current group is evaluated (the single
+    // view mapping has no registers to spare for them at three waves).
+    constexpr bool PF = !(P == 1 && VPL == 1);
+    float4 nq, nsh;
+    float nw0, nw1, nw2;
+    if constexpr (PF) load_rec(0, nq, nsh, nw0, nw1, nw2);
     for (int lc = 0; lc < K; lc += P) {
       const bool own = lc + j < K;
-      const int lo = own ? lc + j : K - 1;
-      const int64_t oi = static_cast<int64_t>(lo) * N + i;
-      const float4 q = S::load4(a.quat, oi);
-      const float4 sh = S::load4(a.shape, oi);
-      float w0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
-      float w1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
-      float w2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
+      float4 q, sh;
+      float w0, w1, w2;
+      if constexpr (PF) {
+        q = nq; sh = nsh; w0 = nw0; w1 = nw1; w2 = nw2;
+        if (lc + P < K) load_rec(lc + P, nq, nsh, nw0, nw1, nw2);
+      } else {
+        load_rec(lc, q, sh, w0, w1, w2);
+      }
       double xa[3], za[3], lamd, ad, kd;
       // what the gradient write-out needs besides the sums: the frame's own
       // parameters (f) and, for the paper's raw values, the derivative of

@@ -118,7 +118,26 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
   const float* base = (a.dirs != nullptr) ? a.dirs : a.means;
   const float b0 = base[3 * i + 0], b1 = base[3 * i + 1], b2 = base[3 * i + 2];
 
+  // upstream gradients of a view chunk, loaded one chunk ahead of their use
+  // so that the load's latency hides behind the current chunk's arithmetic
+  float gq[VPL][3];
+  auto load_grad = [&](int c0_, float (&g)[VPL][3]) {
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) {
+      const int v = c0_ + j + P * t;
+      const int64_t o = (static_cast<int64_t>(v < V ? v : 0) * N + i) * 3;
+      g[t][0] = a.grad_rgb[o + 0];
+      g[t][1] = a.grad_rgb[o + 1];
+      g[t][2] = a.grad_rgb[o + 2];
+    }
+  };
+  if constexpr (BWD) load_grad(0, gq);
+
   for (int v0 = 0; v0 < V; v0 += P * VPL) {
+    float gn[VPL][3];
+    if constexpr (BWD) {
+      if (v0 + P * VPL < V) load_grad(v0 + P * VPL, gn);
+    }
 #pragma unroll
     for (int t = 0; t < VPL; ++t) {
       const int v = v0 + j + P * t;
@@ -147,7 +166,7 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
         a.rgb[o + 2] = r2;
       }
       if constexpr (BWD) {
-        const float g0 = a.grad_rgb[o + 0], g1 = a.grad_rgb[o + 1], g2 = a.grad_rgb[o + 2];
+        const float g0 = gq[t][0], g1 = gq[t][1], g2 = gq[t][2];
         float beta[16];
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
@@ -162,6 +181,14 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
         gm0 = fmaf(gx - pr * x, ri, gm0);
         gm1 = fmaf(gy - pr * y, ri, gm1);
         gm2 = fmaf(gz - pr * z, ri, gm2);
+      }
+    }
+    if constexpr (BWD) {
+#pragma unroll
+      for (int t = 0; t < VPL; ++t) {
+        gq[t][0] = gn[t][0];
+        gq[t][1] = gn[t][1];
+        gq[t][2] = gn[t][2];
       }
     }
   }
