@@ -61,7 +61,8 @@ namespace nasg {
 // direction-gradient partials are summed over the lane group at the end (DPP).
 // For few views this spreads a primitive over P lanes (P lobes prepared and
 // loaded at once) instead of one lane walking all of them.
-template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR = false, bool BC = false>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR = false, bool BC = false,
+          bool PF = !(P == 1 && VPL == 1)>
 __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j,
                                           const LogEntry* ltab) {
   using S = Store<BF16>;
@@ -100,10 +101,9 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       w1_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 1) * N + i);
       w2_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 2) * N + i);
     };
-    // Where a lane meets several views per lobe, the next lobe group's
-    // records are loaded while the current group is evaluated (the single
-    // view mapping has no registers to spare for them at three waves).
-    constexpr bool PF = !(P == 1 && VPL == 1);
+    // PF: the next lobe group's records are loaded while the current group
+    // is evaluated (by default where a lane meets several views per lobe; the
+    // single-view mapping has no registers to spare for them at three waves).
     float4 nq, nsh;
     float nw0, nw1, nw2;
     if constexpr (PF) load_rec(0, nq, nsh, nw0, nw1, nw2);
@@ -337,7 +337,7 @@ __device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int
   for (int m = 0; m < iters; ++m) {
     const int64_t base = start + static_cast<int64_t>(m) * kPrimsPerPass;
     if (base >= a.n) break;  // uniform across the block
-    nasg_body<P, VPL, true, false, ANG, false>(a, base + threadIdx.x / P,
+    nasg_body<P, VPL, true, false, ANG, false, false, false>(a, base + threadIdx.x / P,
                                         static_cast<int>(threadIdx.x & (P - 1)), ltab);
   }
 }
