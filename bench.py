@@ -355,10 +355,12 @@ def worst_scaled(rep):
 def profile_other(args, log):
     """Counter-collection mode of the single-camera, bf16 K=16, paper-params and
     uneven-batch workloads: only the launch their bench line times (the
-    persistent batch with --tile-iters / --blocks-per-cu), --steps times."""
+    persistent batch with the tuner's cached tile, or --tile-iters /
+    --blocks-per-cu), --steps times."""
     import torch
 
     import paper_2606_09794_amd as P
+    from paper_2606_09794_amd import autotune
     import workloads as W
     if args.workload in ("single-camera", "bf16-k16", "paper-params"):
         param = "angles" if args.workload == "paper-params" else "quat"
@@ -385,12 +387,14 @@ def profile_other(args, log):
             dd["grads"] = P.nasg_grad_buffers(sc.workload.k, sc.workload.n, "cuda")
             dd["rgb"] = torch.empty((sc.workload.v, sc.workload.n, 3), device="cuda")
             dev.append(dd)
-        plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=args.tile_iters,
-                               blocks_per_cu=args.blocks_per_cu)
+        ti, bpc = autotune.batch_defaults()
+        ti = ti if args.tile_iters is None else args.tile_iters
+        bpc = bpc if args.blocks_per_cu is None else args.blocks_per_cu
+        plan = P.NasgBatchPlan(dev, norm=args.norm, tile_iters=ti, blocks_per_cu=bpc)
         for _ in range(args.steps):
             plan.run()
         info = {"scenes": len(scenes), "evals": sum(s.workload.n * s.workload.v for s in scenes),
-                "tile_iters": args.tile_iters, "blocks_per_cu": args.blocks_per_cu,
+                "tile_iters": ti, "blocks_per_cu": bpc,
                 "algorithmic_bytes_per_launch": sum(algorithmic_bytes(s.workload.n, s.workload.k,
                                                                       s.workload.v) for s in scenes)}
     else:
@@ -807,10 +811,12 @@ def main():
                          "--workload single-camera, bf16-k16, paper-params or uneven-batch, "
                          "that workload's timed launch only")
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--tile-iters", type=int, default=8,
-                    help="with --profile --workload uneven-batch: tile passes per work item")
-    ap.add_argument("--blocks-per-cu", type=int, default=4,
-                    help="with --profile --workload uneven-batch: persistent blocks per CU")
+    ap.add_argument("--tile-iters", type=int, default=None,
+                    help="with --profile --workload uneven-batch: tile passes per work item "
+                         "(default: the tuner's cached choice, as the bench line uses)")
+    ap.add_argument("--blocks-per-cu", type=int, default=None,
+                    help="with --profile --workload uneven-batch: persistent blocks per CU "
+                         "(default: the tuner's cached choice)")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "single-camera", "bf16-k16", "uneven-batch", "paper-params",
                              "families", "training-view"],
