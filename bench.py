@@ -78,12 +78,24 @@ def _code_only(text: str) -> str:
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
+def _choices_only(text: str) -> str:
+    """A tuning table reduced to its choices (lane mappings, block sizes, batch
+    tile): the timings recorded beside them do not change the launches."""
+    def strip(x):
+        if isinstance(x, dict):
+            return {k: strip(v) for k, v in x.items() if k not in ("ms", "n", "sweep_ms")}
+        return x
+    return json.dumps(strip(json.loads(text)), sort_keys=True)
+
+
 def kernel_source_hash(files=APPEARANCE_SOURCES):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_09794_amd", "csrc")
     for f in files:
         with open(os.path.join(csrc, f)) as fh:
-            h.update(os.path.basename(f).encode() + _code_only(fh.read()).encode())
+            text = fh.read()
+        body = _choices_only(text) if f.endswith(".json") else _code_only(text)
+        h.update(os.path.basename(f).encode() + body.encode())
     return h.hexdigest()[:16]
 
 

@@ -51,6 +51,33 @@
 
 namespace nasg {
 
+// The paper's raw lobe values activated (Supplementary C): lam = e^u,
+// a = e^u, k = 20 (tanh u + 1), w = tanh u, with the derivatives of k and w.
+// A called function: once per lobe, and kept out of line its FP64 series do
+// not count against the evaluating kernel's registers.
+struct Activated {
+  double lam, a, k;
+  float dk;
+  float w[3], dw[3];
+};
+__device__ __noinline__ Activated activate_raw(float4 sh, float w0, float w1, float w2, bool car) {
+  Activated r;
+  double em1, dkd = 0.0;
+  exp_full(sh.x, r.lam, em1);
+  exp_full(sh.y, r.a, em1);
+  r.k = 0.0;
+  if (car) k_activation(sh.z, r.k, dkd);
+  r.dk = static_cast<float>(dkd);
+  const float w[3] = {w0, w1, w2};
+  for (int c = 0; c < 3; ++c) {
+    double t, sc;
+    tanh_sech(w[c], t, sc);
+    r.w[c] = static_cast<float>(t);
+    r.dw[c] = static_cast<float>(sc * sc);
+  }
+  return r;
+}
+
 // One primitive-lane-group's work: primitive `prim` (may be >= n for tail
 // lanes, which compute on a real primitive and write nothing), lane j of P.
 // NOCAR: the NASG lobe (Supplementary E): no carrier (k = zeta = 0) and the
@@ -125,25 +152,19 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
       float dlam_du = 1.f, da_du = 1.f, dk_du = 1.f, dw0 = 1.f, dw1 = 1.f, dw2 = 1.f;
       lobe_frame<ANG>(q, xa, za, f);
       if constexpr (ANG) {
-        // lam = e^u, a = e^u, k = 20 (tanh u + 1), w = tanh u (Supplementary C)
-        double em1, dkd = 0.0;
-        exp_full(sh.x, lamd, em1);
-        exp_full(sh.y, ad, em1);
-        kd = 0.0;
-        if constexpr (!NOCAR) k_activation(sh.z, kd, dkd);
-        double t, sc;
-        tanh_sech(w0, t, sc);
-        w0 = static_cast<float>(t);
-        dw0 = static_cast<float>(sc * sc);
-        tanh_sech(w1, t, sc);
-        w1 = static_cast<float>(t);
-        dw1 = static_cast<float>(sc * sc);
-        tanh_sech(w2, t, sc);
-        w2 = static_cast<float>(t);
-        dw2 = static_cast<float>(sc * sc);
+        const Activated act = activate_raw(sh, w0, w1, w2, !NOCAR);
+        lamd = act.lam;
+        ad = act.a;
+        kd = act.k;
+        w0 = act.w[0];
+        w1 = act.w[1];
+        w2 = act.w[2];
+        dw0 = act.dw[0];
+        dw1 = act.dw[1];
+        dw2 = act.dw[2];
         dlam_du = static_cast<float>(lamd);
         da_du = static_cast<float>(ad);
-        dk_du = static_cast<float>(dkd);
+        dk_du = act.dk;
       } else {
         lamd = sh.x;
         ad = sh.y;
