@@ -248,10 +248,21 @@ def upload(w, device="cuda"):
                 sh=t(w.sh))
 
 
-def time_launches(fn, steps, warmup):
+def time_launches(fn, steps, warmup, settle=0.25):
     """Mean ms per call of fn() over `steps` calls, HIP events on the current
-    stream (the stream the kernels are launched on)."""
+    stream (the stream the kernels are launched on). Before the `warmup` calls,
+    fn() runs untimed for `settle` seconds: the GPU leaves its idle clock over
+    the first tens of milliseconds of load (a kernel trace shows the first
+    launches of a fresh run up to 25 % slower than the steady state), and every
+    measurement here follows host work that lets it idle."""
     import torch
+    if settle > 0:
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            torch.cuda.synchronize()
+            if time.perf_counter() - t0 >= settle:
+                break
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -299,6 +310,7 @@ def stream_ceiling(gib=2, reps=3):
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     lib = L.lib()
     out, sweep = {}, {}
+    settle = 0.25      # once, before the first point: the sweep itself keeps the GPU busy
     for mode, name, moved in ((L.STREAM_READ, "read", nbytes), (L.STREAM_WRITE, "write", nbytes),
                               (L.STREAM_COPY, "copy", 2 * nbytes)):
         best = None
@@ -308,7 +320,8 @@ def stream_ceiling(gib=2, reps=3):
                     run = lambda: L.check(lib.nasg_hbm_stream(  # noqa: E731
                         mode, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, grid,
                         unroll, nt, stream), "nasg_hbm_stream")
-                    ms = time_launches(run, reps, 1)
+                    ms = time_launches(run, reps, 1, settle=settle)
+                    settle = 0.0
                     gbs = moved / ms / 1e6
                     sweep[f"{name}_g{grid}_u{unroll}_nt{nt}"] = round(gbs, 1)
                     if best is None or gbs > best["GB_s"]:
