@@ -12,6 +12,8 @@ through the C ABI, against the FP64 oracle on the same stored values.
   sweep against 50-digit values), through several lane mappings;
 * camera-mode workloads whose sharp lobes (Lam up to 1e6) are aimed at the
   cameras, at the tuned 16-view mapping;
+* lobes on both sides of lam = 1/2 and Lam = 3/2, where the normaliser
+  changes between its FP32 and FP64 code;
 each in float32 and bfloat16 storage (the oracle sees the dequantised
 values) and with both normalisers. Bar: scaled error <= 1e-5 element-wise on
 every output and gradient; the plain relative error is printed beside it.
@@ -87,6 +89,15 @@ def test_sharp_lobes_aimed_at_cameras(dtype, norm):
     its peak and fifteen far from it, at the tuned 16-view mapping."""
     _run_and_check(E.aimed_workload(21 + (dtype == "bf16"), 1501, 8, 16, dtype), norm,
                    "aimed sharp lobes")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("norm", ["exact", "approx"])
+def test_normaliser_precision_switch(dtype, norm):
+    """Lobes on both sides of lam = 1/2 and Lam = 3/2, where the kernel moves
+    between its FP32 and FP64 normaliser, in every branch of Psi and with
+    zeta at 0, pi/2 and next to pi."""
+    _run_and_check(E.switch_grid(dtype), norm, "precision switch")
 
 
 def test_aimed_single_camera():

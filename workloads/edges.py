@@ -15,6 +15,9 @@ integral are numerically delicate:
 * ``k0``           k = 0 exactly
 * ``carrier_zero`` k d.x + zeta = pi up to the rounding of the stored zeta
 
+``switch_grid`` places lobes on both sides of lam = 1/2 and of
+Lam = lam (1 + a) = 3/2, where an evaluator may change its arithmetic.
+
 A case is built from a vector ``u`` of uniform draws in [0, 1) (numpy's
 seeded generator here, Hypothesis in the oracle's property tests), so both
 consumers share the region definitions. Frames come from a table of
@@ -277,4 +280,32 @@ def aimed_workload(seed: int, n: int, k: int, v: int, dtype: str = "f32") -> Wor
     grad = rng.standard_normal((v, n, 3)).astype(np.float32)
     w = Workload(n=n, k=k, v=v, quat=np.ascontiguousarray(quat), shape=np.ascontiguousarray(shape),
                  rgbw=np.ascontiguousarray(rgbw), c0=c0, means=means, cams=cams, grad_rgb=grad)
+    return _finish(w, dtype)
+
+
+def switch_grid(dtype: str = "f32") -> Workload:
+    """Lobes around lam = 1/2 and Lam = lam (1 + a) = 3/2: lam in {0.49, 0.5,
+    0.51, 1}, Lam in {1.49, 1.5, 1.51, 3}, k in {0, 0.3, Lam, Lam + 2, 6} (the
+    hyperbolic, series and sine branches of the normaliser's sinhc), zeta in
+    {0, pi/2, pi - 1e-3}, each viewed at the peak and one peak width off (one
+    lobe and one raw view per primitive)."""
+    rows = []
+    fr = AXIS_FRAMES[5]
+    for lam in (0.49, 0.5, 0.51, 1.0):
+        for big in (1.49, 1.5, 1.51, 3.0):
+            a = big / lam - 1.0
+            for k in (0.0, 0.3, big, big + 2.0, 6.0):
+                for zeta in (0.0, 0.5 * math.pi, math.pi - 1e-3):
+                    for wd in (0.0, 1.0):
+                        rows.append((fr, (lam, a, k, zeta),
+                                     _perp_dir(fr, 1.0, wd / math.sqrt(big), 0.7)))
+    n = len(rows)
+    rng = np.random.default_rng(91)
+    quat = np.asarray([r[0][0] for r in rows], np.float32)[None]
+    shape = np.asarray([r[1] for r in rows], np.float32)[None]
+    dirs = np.asarray([r[2] for r in rows], np.float32)
+    rgbw = rng.standard_normal((1, 3, n), dtype=np.float32)
+    grad = rng.standard_normal((1, n, 3), dtype=np.float32)
+    w = Workload(n=n, k=1, v=1, quat=np.ascontiguousarray(quat), shape=np.ascontiguousarray(shape),
+                 rgbw=rgbw, c0=np.zeros((n, 3), np.float32), dirs=dirs, grad_rgb=grad)
     return _finish(w, dtype)
