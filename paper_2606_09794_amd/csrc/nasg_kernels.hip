@@ -280,17 +280,21 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
             // the FP32 difference would carry its absolute error into E kappa
             const float Ek = static_cast<float>(Ekd);
             const float T2 = fmaf(two_lam, Ek, 1.f);   // 2 lam E kappa + 1
-            acc_a = fmaf(qG * T2 * LR, dx * dx, acc_a);   // ln kappa tau/a = LR (d.x)^2
             const float Sth = (peak ? -scp : scp) * Npe;      // N p E dc/dtheta
             const float gS = gG * Sth;
             acc_k = fmaf(gS, dx, acc_k);
             acc_z += gS;
-            const float GTLR = G * T2 * LR;
-            const float sx = fmaf(GTLR, two_an * dx, Sth * kf);
+            // qT = dL/dG G (2 lam E kappa + 1); uu = qT LR d.x with
+            // LR = ln kappa/(1 - (d.z)^2): a's sum takes uu d.x (ln kappa dtau/da
+            // = LR (d.x)^2), and dL/dG s_x = uu 2a + dL/dG N p E dc/dtheta k
+            const float qT = qG * T2;
+            const float uu = qT * LR * dx;
+            acc_a = fmaf(uu, dx, acc_a);
+            const float gsx = fmaf(uu, two_an, gS * kf);
             const float inv2k = __builtin_amdgcn_rcpf(opf);   // 1/(2 kappa)
-            // s_z = G [(2 lam E kappa + 1) tau Q + lam E], lam E = 2 lam E kappa / (2 kappa)
-            const float sz = G * fmaf(T2 * tau, Q, two_lam * Ek * inv2k);
-            const float gsx = gG * sx, gsz = gG * sz;
+            // dL/dG s_z = dL/dG G [(2 lam E kappa + 1) tau Q + lam E],
+            // lam E = 2 lam E kappa / (2 kappa)
+            const float gsz = fmaf(qT * tau, Q, qG * (two_lam * Ek * inv2k));
             ax0 = fmaf(gsx, sl.df[t][0], ax0);
             ax1 = fmaf(gsx, sl.df[t][1], ax1);
             ax2 = fmaf(gsx, sl.df[t][2], ax2);
