@@ -59,6 +59,26 @@ def test_source_hash_ignores_comments_only():
     assert len(h) == 16 and h == bench.kernel_source_hash(bench.APPEARANCE_SOURCES)
 
 
+def test_source_hash_covers_tuning_choices_not_timings():
+    """The tuning table enters the hash through its choices only: the timings
+    recorded beside them change from box to box without changing a launch."""
+    table = {"arch": "gfx950", "entries": {"1/8/16/0": {"lanes": 4, "views_per_lane": 4,
+                                                          "block": 128, "bcast": 0,
+                                                          "ms": 2.18, "n": 3000000}},
+             "batch": {"tile_iters": 8, "blocks_per_cu": 4, "ms": 10.7, "scenes": 32}}
+    base = bench._choices_only(json.dumps(table))
+    timed = json.loads(json.dumps(table))
+    timed["entries"]["1/8/16/0"]["ms"] = 2.31
+    timed["batch"]["ms"] = 11.2
+    assert bench._choices_only(json.dumps(timed)) == base
+    chosen = json.loads(json.dumps(table))
+    chosen["entries"]["1/8/16/0"]["lanes"] = 8
+    assert bench._choices_only(json.dumps(chosen)) != base
+    chosen = json.loads(json.dumps(table))
+    chosen["batch"]["tile_iters"] = 16
+    assert bench._choices_only(json.dumps(chosen)) != base
+
+
 def test_counters_are_used_only_on_their_sources(tmp_path, monkeypatch):
     """Committed counters price a roofline only while the kernel sources they
     were taken on are unchanged (comment edits aside); otherwise bench.py
