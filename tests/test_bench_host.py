@@ -5,6 +5,7 @@ by hand from the layouts (lobe parameters 44 B in FP32, 22 B in bf16;
 colour and mean 24 B per primitive; 12 B per rgb or upstream-gradient
 triple; 48 SH coefficients 192 B), the comment-blind source hash that ties
 committed counters to kernel sources, and the one-GPU guard."""
+import json
 import os
 import subprocess
 import sys
