@@ -225,7 +225,11 @@ int sh3_eval_bwd(const float* sh, int64_t n, const nasg_views* views,
  * summed over that scene's views), in ONE persistent launch: the scenes are
  * cut into tiles of primitives, the tiles are ordered by cost (tile size x K x
  * V, largest first) and a grid of `blocks_per_cu` blocks per compute unit
- * pulls them from a device work queue. Gradient sums stay per primitive in
+ * pulls them from a device work queue. Each scene runs the lane mapping the
+ * tuning table (nasg_set_tuning, kernel 1, its K and V, float32) holds for
+ * it when the batch kernel carries that mapping -- (1, 1), (1, 2), (1, 4),
+ * (4, 2) or (4, 4) -- and otherwise the smallest of these whose view chunk
+ * holds its views (V = 1, 2, 3..4, 5..8, more). Gradient sums stay per primitive in
  * registers and lanes (the queue counter is the only atomic). Lobe parameters
  * must be float32 (NASG_F32).
  *

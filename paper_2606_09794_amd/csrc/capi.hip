@@ -54,11 +54,13 @@ bool supported(int lanes, int vpl, int bcast) {
 bool block_ok(int b) { return b == 64 || b == 128 || b == 256; }
 
 // Built-in choice when no tuning entry exists (the tuner's picks at K = 8 on
-// MI355X): one lane per primitive up to four views (no slot transfers), then
-// four lanes with two or four views each, so that a lane evaluates several
-// independent lobe-views per step within the registers of two waves per SIMD.
+// MI355X): one lane per primitive up to four views (no slot transfers, and
+// no more view slots than views), then four lanes with two or four views
+// each, so that a lane evaluates several independent lobe-views per step
+// within the registers of two waves per SIMD.
 nasg_tuning heuristic(int32_t v) {
   if (v <= 1) return {1, 1, 256, 0};
+  if (v <= 2) return {1, 2, 256, 0};
   if (v <= 4) return {1, 4, 256, 0};
   if (v <= 8) return {4, 2, 128, 0};
   return {4, 4, 128, 0};
@@ -130,9 +132,22 @@ int check_grad_ptrs(const float* grad_rgb, const nasg_grads* g, const float* rgb
 }
 
 // ---- persistent batches
-// lane mapping by view count, plus 3 for the paper's raw values
-int batch_variant(int32_t v, int32_t param) {
-  return (v <= 1 ? 0 : (v <= 4 ? 1 : 2)) + (param == NASG_PARAM_ANGLES ? 3 : 0);
+// A scene's lane mapping in the persistent batch: the tuning table's choice
+// for its (K, V) when the batch kernel carries that mapping, else the
+// smallest view chunk that holds its views ((1, 1), (1, 2), (1, 4), (4, 2),
+// (4, 4) for V = 1, 2, 3..4, 5..8, more); plus kBatchVariants for the paper's
+// raw values.
+int batch_variant(int32_t k, int32_t v, int32_t param) {
+  int var = v <= 1 ? 0 : v <= 2 ? 1 : v <= 4 ? 2 : v <= 8 ? 3 : 4;
+  const auto& tab = tuning_table();
+  const auto it = tab.find(Key{1, k, v, NASG_F32});   // kernel 1: the NASG backward
+  if (it != tab.end() && it->second.bcast == 0) {
+    for (int c = 0; c < nasg::kBatchVariants; ++c)
+      if (nasg::kBatchLanes[c] == it->second.lanes &&
+          nasg::kBatchViewsPerLane[c] == it->second.views_per_lane)
+        var = c;
+  }
+  return var + (param == NASG_PARAM_ANGLES ? nasg::kBatchVariants : 0);
 }
 
 struct BatchLayout {
@@ -147,7 +162,7 @@ BatchLayout batch_layout(const nasg_scene* sc, int32_t n, int32_t tile_iters) {
   BatchLayout L{};
   L.items_off = align_up(sizeof(nasg::BatchHeader) + sizeof(nasg::BatchScene) * n, 64);
   for (int32_t s = 0; s < n; ++s) {
-    const int64_t tile = static_cast<int64_t>(tile_iters) * (256 / nasg::kBatchLanes[batch_variant(sc[s].views.v, sc[s].p.param)]);
+    const int64_t tile = static_cast<int64_t>(tile_iters) * (256 / nasg::kBatchLanes[batch_variant(sc[s].p.k, sc[s].views.v, sc[s].p.param)]);
     L.n_items += (sc[s].p.n + tile - 1) / tile;
   }
   L.total = L.items_off + sizeof(nasg::BatchItem) * static_cast<size_t>(L.n_items);
@@ -469,7 +484,7 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
     a.norm = norm;
     a.accumulate = 0;
     bs[s].args = a;
-    bs[s].variant = batch_variant(sc.views.v, sc.p.param);
+    bs[s].variant = batch_variant(sc.p.k, sc.views.v, sc.p.param);
     bs[s].tile_iters = tt.tile_iters;
     const int64_t tile = static_cast<int64_t>(tt.tile_iters) * (256 / nasg::kBatchLanes[bs[s].variant]);
     for (int64_t st0 = 0; st0 < sc.p.n; st0 += tile) {
@@ -478,6 +493,9 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
                        nasg::BatchItem{s, 0, st0}});
     }
   }
+  // the layout counted the tiles with the same lane mappings (a tuning change
+  // between the two counts, from another thread, would show here)
+  if (static_cast<int64_t>(tiles.size()) != L.n_items) return NASG_ERR_SHAPE;
   std::stable_sort(tiles.begin(), tiles.end(),
                    [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
   auto* items = reinterpret_cast<nasg::BatchItem*>(host.data() + L.items_off);
@@ -500,7 +518,7 @@ int nasg_batched_plan(const nasg_scene* scenes, int32_t n_scenes, int32_t norm,
   out->token = token;
   out->raw = 0;
   for (int32_t s = 0; s < n_scenes; ++s)
-    if (bs[s].variant >= 3) out->raw = 1;
+    if (bs[s].variant >= nasg::kBatchVariants) out->raw = 1;
   out->pad = 0;
   return NASG_OK;
 }

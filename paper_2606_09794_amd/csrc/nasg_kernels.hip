@@ -390,9 +390,9 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 // head passes n_items. A plan whose token does not match is not run.
 // Two waves per SIMD: the inlined lane mappings would otherwise need more
 // registers than that occupancy allows. RAW: the plan has scenes with the
-// paper's raw values, so all six mappings are inlined; without them only the
-// three quaternion mappings are (4 VGPRs spilled instead of 44), and an item
-// of a raw-value scene, which such a plan never holds, is skipped.
+// paper's raw values, so the five lane mappings are inlined for both
+// parametrisations; without them only the five quaternion mappings are, and
+// an item of a raw-value scene, which such a plan never holds, is skipped.
 template <bool RAW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void nasg_batched_kernel(const BatchHeader* hdr,
@@ -412,22 +412,23 @@ void nasg_batched_kernel(const BatchHeader* hdr,
     if (it >= n_items) break;
     const BatchItem item = load_uniform(items + it);
     const BatchScene sc = load_uniform(scenes + item.scene);
-    if constexpr (RAW) {
-      switch (sc.variant) {
-        case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 1: batch_tile<1, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 2: batch_tile<4, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 3: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 4: batch_tile<1, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-        default: batch_tile<4, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
-      }
-    } else {
-      switch (sc.variant) {
-        case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 1: batch_tile<1, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        case 2: batch_tile<4, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
-        default: break;
-      }
+    switch (sc.variant) {
+      case 0: batch_tile<1, 1, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 1: batch_tile<1, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 2: batch_tile<1, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 3: batch_tile<4, 2, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      case 4: batch_tile<4, 4, false>(sc.args, item.start, sc.tile_iters, ltab); break;
+      default:
+        if constexpr (RAW) {
+          switch (sc.variant) {
+            case 5: batch_tile<1, 1, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+            case 6: batch_tile<1, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+            case 7: batch_tile<1, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+            case 8: batch_tile<4, 2, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+            default: batch_tile<4, 4, true>(sc.args, item.start, sc.tile_iters, ltab); break;
+          }
+        }
+        break;
     }
   }
 }

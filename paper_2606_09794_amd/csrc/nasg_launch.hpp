@@ -102,8 +102,9 @@ static_assert(sizeof(BatchHeader) == 64, "batch header layout");
 
 struct BatchScene {
   NasgArgs args;
-  int32_t variant;     // lane mapping: 0 = (1 lane, 1 view), 1 = (1, 4), 2 = (4, 4);
-                       // 3..5: the same for the paper's raw values
+  int32_t variant;     // lane mapping (lanes, views per lane): 0 = (1, 1), 1 = (1, 2),
+                       // 2 = (1, 4), 3 = (4, 2), 4 = (4, 4); 5..9: the same for the
+                       // paper's raw values
   int32_t tile_iters;
 };
 
@@ -113,7 +114,9 @@ struct BatchItem {
   int64_t start;       // first primitive of the tile
 };
 
-constexpr int kBatchLanes[6] = {1, 1, 4, 1, 1, 4};
+constexpr int kBatchVariants = 5;   // lane mappings per parametrisation
+constexpr int kBatchLanes[2 * kBatchVariants] = {1, 1, 1, 4, 4, 1, 1, 1, 4, 4};
+constexpr int kBatchViewsPerLane[2 * kBatchVariants] = {1, 2, 4, 2, 4, 1, 2, 4, 2, 4};
 
 hipError_t launch_batched(const BatchHeader* hdr, const BatchScene* scenes, const BatchItem* items,
                           uint32_t* counter, uint64_t token, int grid, bool raw, hipStream_t s);

@@ -97,3 +97,51 @@ def test_batched_graph_replays_match_eager():
             now = _snapshot(d)
             for k in e:
                 assert torch.equal(now[k], e[k]), (rep, w.n, k)
+
+
+@pytest.mark.parametrize("follow_table", [False, True])
+def test_batched_lane_mapping_by_views_and_tuning(follow_table):
+    """Scenes with 2, 3, 5, 8, 9 and 20 views (one with the paper's raw values)
+    in one persistent launch. Each takes the smallest carried lane mapping
+    whose view chunk holds its views, or, with a tuning entry for its (K, V)
+    that names a carried mapping, that one (here (1 lane, 4 views) for all);
+    either way it equals the single-scene launch with the same mapping bitwise."""
+    specs = [(600, 8, 2, "quat"), (500, 4, 3, "quat"), (700, 8, 5, "quat"), (400, 16, 8, "quat"),
+             (300, 8, 9, "quat"), (350, 4, 20, "quat"), (450, 4, 8, "angles")]
+    keys = sorted({(k, v) for _, k, v, _ in specs})
+    saved = {key: P.get_tuning(1, key[0], key[1], 0) for key in keys}
+    try:
+        for k, v in keys:
+            if follow_table:
+                P.set_tuning(1, k, v, 0, 1, 4, 256)
+            else:
+                P.set_tuning(1, k, v, 0, 0, 0)      # no entry: the view-count choice
+        scenes = []
+        for s, (n, k, v, par) in enumerate(specs):
+            w = W.draw_workload(80 + s, n, k, v, param=par)
+            d = upload(w)
+            d["param"] = par
+            d["grads"] = P.nasg_grad_buffers(k, n, "cuda")
+            d["rgb"] = torch.empty((v, n, 3), device="cuda")
+            scenes.append((w, d))
+        plan = P.NasgBatchPlan([d for _, d in scenes], tile_iters=2, blocks_per_cu=2)
+        for _, d in scenes:
+            _poison(d)
+        plan.run()
+        torch.cuda.synchronize()
+        for w, d in scenes:
+            got = _snapshot(d)
+            rgb = torch.empty_like(d["rgb"])
+            ref = P.nasg_eval_bwd(d["quat"], d["shape"], d["rgbw"], d["c0"], d["grad_rgb"],
+                                  means=d["means"], cams=d["cams"], param=d["param"], rgb_out=rgb)
+            torch.cuda.synchronize()
+            for key in ref:
+                assert torch.equal(got[key], ref[key]), (w.n, w.k, w.v, d["param"], key)
+            assert torch.equal(got["rgb"], rgb), (w.n, w.k, w.v, d["param"], "rgb")
+        w, d = scenes[3]
+        ref, scale = oracle_nasg(w, "exact")
+        for name in ("quat", "shape", "rgbw"):
+            compare(d["grads"][name].cpu().numpy(), ref[name], scale[name], name, 1e-5)
+    finally:
+        for (k, v), t in saved.items():
+            P.set_tuning(1, k, v, 0, t[0], t[1], t[2], t[3])
