@@ -511,18 +511,21 @@ def measure_bf16_k16(norm, steps, warmup, log, n=6_000_000, ceiling=None):
             "bf16_quantisation_cost_vs_fp32_values": qcost}
 
 
-def measure_uneven_batch(norm, steps, warmup, log, ceiling=None, tune=True):
-    """32 scenes (N log-uniform in [5e4, 2e6], K in {4, 8, 16}, V in {1, 4, 16})
-    in one persistent fused launch with the tuner's (tile passes, blocks per CU),
-    its hipGraph replay and per-scene launches; sampled parity per scene."""
+def measure_uneven_batch(norm, steps, warmup, log, ceiling=None, tune=True, n_scenes=32,
+                         scale=1.0, parity_every=4):
+    """`n_scenes` scenes (N log-uniform in [5e4, 2e6] times `scale`, K in
+    {4, 8, 16}, V in {1, 4, 16}) in one persistent fused launch with the
+    tuner's (tile passes, blocks per CU), its hipGraph replay and per-scene
+    launches; sampled parity on every `parity_every`-th scene."""
     import torch
 
     import paper_2606_09794_amd as P
     import workloads as W
     from paper_2606_09794_amd import autotune
     t0 = time.perf_counter()
-    scenes = W.config4()
-    log(f"uneven batch: generated {len(scenes)} scenes, {sum(s.workload.n for s in scenes)} primitives "
+    scenes = W.config4(n_scenes=n_scenes, scale=scale)
+    tag = f"uneven batch ({len(scenes)} scenes)"
+    log(f"{tag}: generated {len(scenes)} scenes, {sum(s.workload.n for s in scenes)} primitives "
         f"in {time.perf_counter() - t0:.1f}s")
     dev = []
     for sc in scenes:
@@ -563,17 +566,18 @@ def measure_uneven_batch(norm, steps, warmup, log, ceiling=None, tune=True):
     graph.replay()
     torch.cuda.synchronize()
     worst = {}
-    for sc, dd in zip(scenes[::4], dev[::4]):
+    for sc, dd in zip(scenes[::parity_every], dev[::parity_every]):
         rep = _sampled(sc.workload, dict(dd["grads"], rgb=dd["rgb"]), norm, n_sample=64)
         for kk, vv in rep.items():
             cur = worst.get(kk)
             if cur is None or vv["scaled"]["max"] > cur["scaled"]["max"]:
                 worst[kk] = vv
-    log(f"uneven batch: persistent {ms:.3f} ms, graph {ms_graph:.3f} ms, per-scene {ms_sep:.3f} ms "
+    log(f"{tag}: persistent {ms:.3f} ms, graph {ms_graph:.3f} ms, per-scene {ms_sep:.3f} ms "
         f"(tile {ti}, {bpc} blocks/CU), parity worst scaled {worst_scaled(worst):.2e}")
     del graph, plan, dev
     torch.cuda.empty_cache()
-    return {"workload": f"{len(scenes)} scenes (N log-uniform in [5e4, 2e6], K in {{4,8,16}}, "
+    lo, hi = (f"{x:.0e}".replace("e+0", "e") for x in (5e4 * scale, 2e6 * scale))
+    return {"workload": f"{len(scenes)} scenes (N log-uniform in [{lo}, {hi}], K in {{4,8,16}}, "
                         f"V in {{1,4,16}}), one persistent fused fwd+bwd launch, {norm} normaliser",
             "scenes": len(scenes), "primitives": sum(s.workload.n for s in scenes), "evals": evals,
             "tile_iters": ti, "blocks_per_cu": bpc,
@@ -999,6 +1003,11 @@ def main():
         torch.cuda.empty_cache()
         cmp["uneven_batch_32_scenes"] = measure_uneven_batch(args.norm, args.steps, args.warmup, log,
                                                              ceiling=ceiling)
+        torch.cuda.empty_cache()
+        # the case a single persistent launch is for: many small scenes
+        cmp["uneven_batch_256_small_scenes"] = measure_uneven_batch(
+            args.norm, args.steps, args.warmup, log, ceiling=ceiling, n_scenes=256, scale=0.02,
+            parity_every=16)
         out["compare"] = cmp
         out["cpu_baseline"] = cpu_baseline(w, prims=args.cpu_prims,
                                            norm_code=0 if args.norm == "exact" else 1)
