@@ -3,7 +3,9 @@
 // - storage decode for float32 / bfloat16 lobe parameters,
 // - reductions over the `P` consecutive lanes that share a primitive, done
 //   with DPP row operations (no LDS, no atomics, fixed order),
-// - the per-lobe normaliser (Section 5.1) and its log-derivatives in FP64.
+// - the per-lobe normaliser (Section 5.1) and its log-derivatives, in FP64
+//   and, for the range of lam and lam (1 + a) where nothing cancels badly,
+//   in FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>

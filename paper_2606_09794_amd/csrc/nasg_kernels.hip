@@ -6,7 +6,7 @@
 // v0 + j + P*t, t < VPL: the direction, upstream gradient, colour and
 // direction-gradient accumulators, in registers). Lobes are taken P at a time
 // and lane j owns lobe lc + j: it loads that lobe (structure-of-arrays,
-// coalesced across primitives) and prepares its constants once (FP64 frame,
+// coalesced across primitives) and prepares its constants once (the FP64 frame,
 // normaliser and its log-derivatives). Then, P times, every lane evaluates its
 // own lobe against the view slot it holds and passes the slot on to the next
 // lane of the group (ds_bpermute), so each owned lobe meets every view of the
@@ -24,7 +24,8 @@
 // FP64 (exp turns its absolute error into a relative error of G) and only
 // its final exponential, the carrier's sine/cosine and all gradient factors
 // and accumulations are FP32. The normaliser and its log-derivatives are
-// FP64, once per lobe.
+// formed once per lobe: in FP32 where lam >= 1/2 and lam (1 + a) >= 3/2
+// (with the cancellation-prone pieces in FP64), in FP64 elsewhere.
 //
 // Value (Section 5.1): G = N p E c, kappa = (d.z + 1)/2,
 //   tau = a (d.x)^2 / (1 - (d.z)^2), E = kappa^tau, p = exp(2 lam (E kappa - 1)),
