@@ -409,6 +409,24 @@ enum { NASG_STREAM_READ = 0, NASG_STREAM_WRITE = 1, NASG_STREAM_COPY = 2 };
 int nasg_hbm_stream(int32_t mode, const void* src, void* dst, int64_t bytes, int32_t blocks,
                     int32_t unroll, int32_t nontemporal, void* stream);
 
+/* ---- camera-spacing statistic (Section 4, implementation details) ---------
+ * The appearance learning rates are scaled with how densely the cameras
+ * sample the scene: d_knn is the distance from each camera centre to its k
+ * nearest other centres (the paper uses k = 3), averaged over the k
+ * neighbours and then over the cameras. `centres` is [n_cams][3] FP64,
+ * finite; per_camera[i] (FP64, n_cams entries) receives camera i's mean
+ * distance to its k nearest others (coincident centres count, at distance
+ * 0), and mean[0] (one FP64) their average over the cameras, summed in a
+ * fixed order, so repeated calls give identical bits. All three are device
+ * pointers, 8-byte aligned, owned by the caller. 1 <= k <= NASG_KNN_MAX_K and
+ * k < n_cams <= NASG_KNN_MAX_CAMERAS, else NASG_ERR_SHAPE; NULL pointers
+ * give NASG_ERR_NULL, misaligned ones NASG_ERR_ALIGN. Asynchronous on
+ * `stream` (two launches); nothing is allocated.                          */
+enum { NASG_KNN_MAX_K = 32, NASG_KNN_MAX_CAMERAS = 1 << 16 };
+
+int nasg_camera_knn(const double* centres, int32_t n_cams, int32_t k, double* per_camera,
+                    double* mean, void* stream);
+
 /* Human-readable name of a status code (static storage).                    */
 const char* nasg_status_string(int status);
 

@@ -18,16 +18,24 @@ from __future__ import annotations
 import math
 
 
+def knn_one(centres, i, k=3):
+    """Mean distance from camera i to its k nearest other cameras."""
+    pts = [tuple(float(c) for c in p) for p in centres]
+    ds = sorted(math.dist(pts[i], q) for j, q in enumerate(pts) if j != i)
+    return sum(ds[:k]) / k
+
+
+def knn_per_camera(centres, k=3):
+    """knn_one for every camera, in camera order."""
+    if len(centres) <= k:
+        raise ValueError("need more than k cameras")
+    return [knn_one(centres, i, k) for i in range(len(centres))]
+
+
 def knn_distance(centres, k=3):
     """Average over cameras of the mean distance to the k nearest others."""
-    pts = [tuple(float(c) for c in p) for p in centres]
-    if len(pts) <= k:
-        raise ValueError("need more than k cameras")
-    total = 0.0
-    for i, p in enumerate(pts):
-        ds = sorted(math.dist(p, q) for j, q in enumerate(pts) if j != i)
-        total += sum(ds[:k]) / k
-    return total / len(pts)
+    per = knn_per_camera(centres, k)
+    return math.fsum(per) / len(per)
 
 
 def rate_scales(d_knn, d_ref, beta=2.0, gamma=0.6):

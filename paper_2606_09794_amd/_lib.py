@@ -20,6 +20,7 @@ FAMILIES = {"nasgabor": 0, "nasg": 1, "sg": 2, "sb": 3, "sc": 4, "asg": 5}
 KERNEL_NASG_FWD, KERNEL_NASG_BWD, KERNEL_SH_FWD, KERNEL_SH_BWD = 0, 1, 2, 3
 STREAM_READ, STREAM_WRITE, STREAM_COPY = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20
+KNN_MAX_K, KNN_MAX_CAMERAS = 32, 1 << 16
 
 
 class NasgParams(C.Structure):
@@ -95,6 +96,8 @@ EXPORTS = {
                                           C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "nasg_hbm_stream": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_void_p]),
+    "nasg_camera_knn": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "nasg_status_string": (C.c_char_p, [C.c_int]),
     "nasg_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(NasgTuning)]),

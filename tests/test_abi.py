@@ -221,6 +221,20 @@ def test_hbm_stream_rejects(lib):
     assert s(nb=0) == 0                      # nothing to stream, nothing launched
 
 
+def test_camera_knn_rejects(lib):
+    f = lambda c=FAKE, n=40, k=3, per=FAKE + 4096, mean=FAKE + 8192: \
+        lib.nasg_camera_knn(c, n, k, per, mean, None)  # noqa: E731
+    assert f(k=0) == -2
+    assert f(k=L.KNN_MAX_K + 1) == -2
+    assert f(n=3) == -2                      # needs more than k cameras
+    assert f(n=L.KNN_MAX_CAMERAS + 1) == -2
+    assert f(c=None) == -1
+    assert f(per=None) == -1
+    assert f(mean=None) == -1
+    assert f(c=FAKE + 4) == -3
+    assert f(mean=FAKE + 8196) == -3
+
+
 def test_raster_fwd_noalloc_rejects(lib):
     """Invalid arguments, and a workspace beyond the fixed scratch, are refused
     on the host before the runtime is touched."""

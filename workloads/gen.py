@@ -154,6 +154,31 @@ def _draw_cams(rng: np.random.Generator, v: int) -> np.ndarray:
     return (10.0 * g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
 
 
+CAMERA_LAYOUTS = ("sphere", "orbit", "forward")
+
+
+def draw_camera_centres(seed: int, n: int, layout: str = "sphere") -> np.ndarray:
+    """[n][3] float64 camera centres in the layouts of the paper's captures:
+    "sphere", directions uniform on a shell of radius 10 (the appearance
+    workloads' cameras); "orbit", a walk-around at radius 4-6 with heights in
+    [0.5, 2.5] and jittered angular steps; "forward", a forward-facing
+    capture, a jittered 2D grid of spacing 0.2 in the plane z = -3."""
+    rng = np.random.default_rng(seed)
+    if layout == "sphere":
+        g = rng.standard_normal((n, 3))
+        return 10.0 * g / np.linalg.norm(g, axis=1, keepdims=True)
+    if layout == "orbit":
+        a = 2 * np.pi * (np.arange(n) + 0.3 * rng.random(n)) / n
+        r = rng.uniform(4.0, 6.0, n)
+        return np.stack([r * np.cos(a), r * np.sin(a), rng.uniform(0.5, 2.5, n)], -1)
+    if layout == "forward":
+        side = int(np.ceil(np.sqrt(n)))
+        ij = np.stack(np.divmod(np.arange(n), side), -1).astype(np.float64)
+        xy = 0.2 * (ij + 0.25 * rng.standard_normal((n, 2)))
+        return np.concatenate([xy, np.full((n, 1), -3.0)], -1)
+    raise ValueError(f"layout must be one of {CAMERA_LAYOUTS}")
+
+
 def draw_workload(seed: int, n: int, k: int, v: int, *, dirs_mode: bool = False,
                   with_grad: bool = True, with_sh: bool = True, dtype: str = "f32",
                   rng: Optional[np.random.Generator] = None, param: str = "quat",
