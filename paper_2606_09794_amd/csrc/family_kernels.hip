@@ -50,11 +50,12 @@ __device__ __forceinline__ void family_body(const NasgArgs& a, int64_t prim, int
       const bool own = lc + j < K;
       const int lo = own ? lc + j : K - 1;
       const int64_t oi = static_cast<int64_t>(lo) * N + i;
-      const float4 q = S::load4(a.quat, oi);
-      const float4 sh = S::load4(a.shape, oi);
-      const float w0 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 0) * N + i);
-      const float w1 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 1) * N + i);
-      const float w2 = S::load1(a.rgbw, (static_cast<int64_t>(lo) * 3 + 2) * N + i);
+      const int64_t wi = static_cast<int64_t>(lo) * 3 * N + i;
+      const float4 q = S::template load4<false>(a.quat, oi);
+      const float4 sh = S::template load4<false>(a.shape, oi);
+      const float w0 = S::template load1<false>(a.rgbw, wi);
+      const float w1 = S::template load1<false>(a.rgbw, wi + N);
+      const float w2 = S::template load1<false>(a.rgbw, wi + 2 * N);
       double xa[3], za[3], ya[3] = {0.0, 0.0, 0.0};
       float f[6];
       lobe_frame<false>(q, xa, za, f);
@@ -182,7 +183,8 @@ __device__ __forceinline__ void family_body(const NasgArgs& a, int64_t prim, int
         if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr)
-            put4(a.g_shape, li, make_float4(fmaf(dlc0, acc_G, acc_p0), acc_p1, 0.f, 0.f), acc_mode);
+            put4<false>(a.g_shape, li, make_float4(fmaf(dlc0, acc_G, acc_p0), acc_p1, 0.f, 0.f),
+                        acc_mode);
           if (a.g_quat != nullptr) {
             float gx[3] = {ax[0], ax[1], ax[2]}, gz[3] = {az[0], az[1], az[2]};
             if constexpr (FAM == kFamAsg) {
@@ -194,9 +196,10 @@ __device__ __forceinline__ void family_body(const NasgArgs& a, int64_t prim, int
               gz[1] += xf[2] * ay[0] - xf[0] * ay[2];
               gz[2] += xf[0] * ay[1] - xf[1] * ay[0];
             }
-            put4(a.g_quat, li, frame_grad<false>(f, xf, zf, gx, gz), acc_mode);
+            put4<false>(a.g_quat, li, frame_grad<false>(f, xf, zf, gx, gz), acc_mode);
           }
-          if (a.g_rgbw != nullptr) put_rgbw(a.g_rgbw, lc + j, N, i, acc_w0, acc_w1, acc_w2, acc_mode);
+          if (a.g_rgbw != nullptr)
+            put_rgbw<false>(a.g_rgbw, lc + j, N, i, acc_w0, acc_w1, acc_w2, acc_mode);
         }
       }
     }

@@ -1,6 +1,7 @@
 // Device-side building blocks of the NASGabor / SH-3 evaluators (gfx950).
 //
-// - storage decode for float32 / bfloat16 lobe parameters,
+// - storage decode for float32 / bfloat16 lobe parameters, and the
+//   nontemporal (streaming) accesses for data used once,
 // - reductions over the `P` consecutive lanes that share a primitive, done
 //   with DPP row operations (no LDS, no atomics, fixed order),
 // - the per-lobe normaliser (Section 5.1) and its log-derivatives, in FP64
@@ -18,30 +19,72 @@ constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
 constexpr double kInvPi = 0.318309886183790671537767526745028724;
 
 // ---------------------------------------------------------------- storage
+// Data that a launch touches once is accessed nontemporally: the streaming
+// cache policy keeps it from displacing what is still to be reused (the
+// cameras, the log table). The lobe records are read, and the lobe gradients
+// written, once per view chunk, so they are streamed only by the kernels of
+// launches whose views fit in one chunk (ONCE); with more chunks each record
+// is read again and each gradient read back for the next chunk's sums, and
+// both stay cached. The per-view colours and upstream gradients ([V][N][3])
+// are streamed where a wave's access covers whole cache lines (one lane per
+// primitive: 64 x 12 bytes); with several lanes per primitive a wave covers
+// 12 bytes of 64/P primitives, neighbouring waves share lines, and plain
+// accesses let the second one find its line cached.
+
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_nt __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ inline T load_once(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ inline void store_once(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+template <bool NT, class T>
+__device__ inline T load_if(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT, class T>
+__device__ inline void store_if(T v, T* p) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
+  }
+}
 
 template <bool BF16>
 struct Store;
 
 template <>
 struct Store<false> {
+  template <bool ONCE>
   __device__ static inline float4 load4(const void* p, int64_t idx) {
-    return reinterpret_cast<const float4*>(p)[idx];
+    const f32x4_nt v = load_if<ONCE>(reinterpret_cast<const f32x4_nt*>(p) + idx);
+    return make_float4(v.x, v.y, v.z, v.w);
   }
+  template <bool ONCE>
   __device__ static inline float load1(const void* p, int64_t idx) {
-    return reinterpret_cast<const float*>(p)[idx];
+    return load_if<ONCE>(reinterpret_cast<const float*>(p) + idx);
   }
 };
 
 template <>
 struct Store<true> {
   // four bfloat16 values packed little-endian in 8 bytes
+  template <bool ONCE>
   __device__ static inline float4 load4(const void* p, int64_t idx) {
-    const uint2 u = reinterpret_cast<const uint2*>(p)[idx];
+    const u32x2_nt u = load_if<ONCE>(reinterpret_cast<const u32x2_nt*>(p) + idx);
     return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                        __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
   }
+  template <bool ONCE>
   __device__ static inline float load1(const void* p, int64_t idx) {
-    return __uint_as_float(static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(p)[idx]) << 16);
+    const uint16_t u = load_if<ONCE>(reinterpret_cast<const uint16_t*>(p) + idx);
+    return __uint_as_float(static_cast<uint32_t>(u) << 16);
   }
 };
 

@@ -90,7 +90,7 @@ __device__ __noinline__ Activated activate_raw(float4 sh, float w0, float w1, fl
 // For few views this spreads a primitive over P lanes (P lobes prepared and
 // loaded at once) instead of one lane walking all of them.
 template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR = false, bool BC = false,
-          bool PF = !(P == 1 && VPL == 1)>
+          bool ONCE = false, bool PF = !(P == 1 && VPL == 1)>
 __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j,
                                           const LogEntry* ltab) {
   using S = Store<BF16>;
@@ -123,11 +123,11 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
     auto load_rec = [&](int lc_, float4& q_, float4& sh_, float& w0_, float& w1_, float& w2_) {
       const int lo_ = lc_ + j < K ? lc_ + j : K - 1;
       const int64_t oi_ = static_cast<int64_t>(lo_) * N + i;
-      q_ = S::load4(a.quat, oi_);
-      sh_ = S::load4(a.shape, oi_);
-      w0_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 0) * N + i);
-      w1_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 1) * N + i);
-      w2_ = S::load1(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 2) * N + i);
+      q_ = S::template load4<ONCE>(a.quat, oi_);
+      sh_ = S::template load4<ONCE>(a.shape, oi_);
+      w0_ = S::template load1<ONCE>(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 0) * N + i);
+      w1_ = S::template load1<ONCE>(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 1) * N + i);
+      w2_ = S::template load1<ONCE>(a.rgbw, (static_cast<int64_t>(lo_) * 3 + 2) * N + i);
     };
     // PF: the next lobe group's records are loaded while the current group
     // is evaluated (by default where a lane meets several views per lobe; the
@@ -320,19 +320,20 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr) {
-            put4(a.g_shape, li,
-                 make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l) * dlam_du,
-                             fmaf(nm.da, acc_G, acc_a) * da_du,
-                             fmaf(nm.dk, acc_G, acc_k) * dk_du, fmaf(nm.dz, acc_G, acc_z)),
-                 acc_mode);
+            put4<ONCE>(a.g_shape, li,
+                       make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l) * dlam_du,
+                                   fmaf(nm.da, acc_G, acc_a) * da_du,
+                                   fmaf(nm.dk, acc_G, acc_k) * dk_du, fmaf(nm.dz, acc_G, acc_z)),
+                       acc_mode);
           }
           if (a.g_quat != nullptr) {
             const float xf[3] = {xf0, xf1, xf2}, zf[3] = {zf0, zf1, zf2};
             const float gx[3] = {ax0, ax1, ax2}, gz[3] = {az0, az1, az2};
-            put4(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
+            put4<ONCE>(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
           }
           if (a.g_rgbw != nullptr)
-            put_rgbw(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1, acc_w2 * dw2, acc_mode);
+            put_rgbw<ONCE>(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1, acc_w2 * dw2,
+                           acc_mode);
         }
       }
     }
@@ -341,17 +342,20 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
   }
 }
 
-template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
+template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC, bool ONCE>
 // One lane and one view per primitive run three waves per SIMD (the few spills
 // land in the once-per-lobe preparation), and so do broadcast views; the other
 // mappings keep two, where the full register budget pays more than a third wave.
+// ONCE: all views fit in one chunk, so the lobe records are read and the
+// lobe gradients written exactly once, both as streaming data.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     BC ? NASG_BC_WAVES : (P == 1 && VPL == 1 ? 3 : 2))))
 void nasg_kernel(const NasgArgs a) {
   __shared__ LogEntry ltab[kLogEntries];
   load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  nasg_body<P, VPL, BWD, BF16, ANG, NOCAR, BC>(a, gt / P, static_cast<int>(gt & (P - 1)), ltab);
+  nasg_body<P, VPL, BWD, BF16, ANG, NOCAR, BC, ONCE>(a, gt / P, static_cast<int>(gt & (P - 1)),
+                                                     ltab);
 }
 
 // ------------------------------------------------------- persistent batch
@@ -363,7 +367,7 @@ __device__ __forceinline__ void batch_tile(const NasgArgs& a, int64_t start, int
   for (int m = 0; m < iters; ++m) {
     const int64_t base = start + static_cast<int64_t>(m) * kPrimsPerPass;
     if (base >= a.n) break;  // uniform across the block
-    nasg_body<P, VPL, true, false, ANG, false, false, false>(a, base + threadIdx.x / P,
+    nasg_body<P, VPL, true, false, ANG, false, false, false, false>(a, base + threadIdx.x / P,
                                         static_cast<int>(threadIdx.x & (P - 1)), ltab);
   }
 }
@@ -455,8 +459,13 @@ template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
 static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
   const int64_t threads = a.n * P;
   const int64_t grid = (threads + block - 1) / block;
-  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC>),
-                     dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
+  if (a.v <= (BC ? VPL : P * VPL)) {
+    hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, true>),
+                       dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, false>),
+                       dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -133,9 +133,9 @@ __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0
     if constexpr (BWD) {
       if (s.has[t]) {
         const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
-        s.gr[t][0] = a.grad_rgb[o + 0];
-        s.gr[t][1] = a.grad_rgb[o + 1];
-        s.gr[t][2] = a.grad_rgb[o + 2];
+        s.gr[t][0] = load_if<P == 1>(&a.grad_rgb[o + 0]);
+        s.gr[t][1] = load_if<P == 1>(&a.grad_rgb[o + 1]);
+        s.gr[t][2] = load_if<P == 1>(&a.grad_rgb[o + 2]);
       } else {
         s.gr[t][0] = s.gr[t][1] = s.gr[t][2] = 0.f;
       }
@@ -185,9 +185,9 @@ __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool 
     for (int t = 0; t < VPL; ++t) {
       if (!s.has[t] || (BC && j != t % P)) continue;
       const int64_t o = (static_cast<int64_t>(BC ? v0 + t : v0 + j + P * t) * N + i) * 3;
-      a.rgb[o + 0] = s.col[t][0];
-      a.rgb[o + 1] = s.col[t][1];
-      a.rgb[o + 2] = s.col[t][2];
+      store_if<P == 1>(s.col[t][0], &a.rgb[o + 0]);
+      store_if<P == 1>(s.col[t][1], &a.rgb[o + 1]);
+      store_if<P == 1>(s.col[t][2], &a.rgb[o + 2]);
     }
   }
   if constexpr (BWD) {
@@ -351,32 +351,46 @@ __device__ __forceinline__ float4 frame_grad(const float (&f)[6], const float (&
   }
 }
 
-// Adds (or writes) a float4 gradient.
+// Adds or writes a float4 gradient. FINAL: the write is the last one, so
+// it streams (the kernels of single-chunk launches); with more view chunks
+// the first chunk's write is read back by the next one and stays cached. The
+// adding branch stores the four words one by one: were both branches one
+// 16-byte store of the same address, the compiler would merge them into a
+// single plain store.
+template <bool FINAL>
 __device__ __forceinline__ void put4(float* base, int64_t li, float4 g, bool acc_mode) {
-  float4* dst = reinterpret_cast<float4*>(base) + li;
+  float* dst = base + 4 * li;
   if (acc_mode) {
-    const float4 o = *dst;
-    g.x += o.x;
-    g.y += o.y;
-    g.z += o.z;
-    g.w += o.w;
+    dst[0] += g.x;
+    dst[1] += g.y;
+    dst[2] += g.z;
+    dst[3] += g.w;
+  } else if constexpr (FINAL) {
+    store_once(f32x4_nt{g.x, g.y, g.z, g.w}, reinterpret_cast<f32x4_nt*>(dst));
+  } else {
+    *reinterpret_cast<float4*>(dst) = g;
   }
-  *dst = g;
 }
 
-// Adds (or writes) a per-lobe colour-weight gradient in the channel-planar
-// layout [K][3][N].
+// Adds or writes a per-lobe colour-weight gradient in the channel-planar
+// layout [K][3][N] (FINAL as for put4).
+template <bool FINAL>
 __device__ __forceinline__ void put_rgbw(float* g_rgbw, int lobe, int64_t N, int64_t i, float r0,
                                          float r1, float r2, bool acc_mode) {
   float* dst = g_rgbw + static_cast<int64_t>(lobe) * 3 * N + i;
   if (acc_mode) {
-    r0 += dst[0];
-    r1 += dst[N];
-    r2 += dst[2 * N];
+    dst[0] += r0;
+    dst[N] += r1;
+    dst[2 * N] += r2;
+  } else if constexpr (FINAL) {
+    store_once(r0, dst);
+    store_once(r1, dst + N);
+    store_once(r2, dst + 2 * N);
+  } else {
+    dst[0] = r0;
+    dst[N] = r1;
+    dst[2 * N] = r2;
   }
-  dst[0] = r0;
-  dst[N] = r1;
-  dst[2 * N] = r2;
 }
 
 }  // namespace nasg

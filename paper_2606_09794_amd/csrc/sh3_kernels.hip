@@ -18,6 +18,16 @@
 // The direction gradient of the homogeneous polynomials is projected onto the
 // sphere's tangent plane through d = e/|e|, so the choice of extension off the
 // sphere does not matter.
+//
+// Each Y_j is s_j M_j with s_j its signed normalisation and M_j a polynomial
+// with small integer coefficients. The kernels fold s_j into the primitive's
+// coefficients as they are loaded (c'_j = s_j c_j), so per view they evaluate
+// only the M_j: rgb = sum c'_j M_j, the direction gradient is that of
+// sum_j beta'_j M_j with beta'_j = g . c'_j (= s_j g . c_j), and the
+// coefficient gradient sum_v g M_j is scaled by s_j once, when it is written.
+// Coefficients and their gradients, read and written once per launch, are
+// streamed; so are the per-view colours and upstream gradients with one lane
+// per primitive, whose accesses then cover whole cache lines.
 #include <hip/hip_runtime.h>
 
 #include "nasg_device.hpp"
@@ -38,58 +48,69 @@ constexpr float c3d = 0.37317633259011540f;
 constexpr float c3e = 1.4453057213202769f;
 }  // namespace shc
 
-__device__ inline void sh_basis(float x, float y, float z, float Y[16]) {
+// signed normalisation s_j of Y_j = s_j M_j (j a compile-time index in the
+// unrolled loops, so every use folds to a literal)
+__device__ constexpr float sh_scale(int j) {
   using namespace shc;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[0] = c0;
-  Y[1] = -c1 * y;
-  Y[2] = c1 * z;
-  Y[3] = -c1 * x;
-  Y[4] = c2a * x * y;
-  Y[5] = -c2a * y * z;
-  Y[6] = c2b * (2.f * zz - xx - yy);
-  Y[7] = -c2a * x * z;
-  Y[8] = c2c * (xx - yy);
-  Y[9] = -c3a * y * (3.f * xx - yy);
-  Y[10] = c3b * x * y * z;
-  Y[11] = -c3c * y * (4.f * zz - xx - yy);
-  Y[12] = c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
-  Y[13] = -c3c * x * (4.f * zz - xx - yy);
-  Y[14] = c3e * z * (xx - yy);
-  Y[15] = -c3a * x * (xx - 3.f * yy);
+  constexpr float s[16] = {c0,  -c1,  c1,  -c1,  c2a, -c2a, c2b, -c2a,
+                           c2c, -c3a, c3b, -c3c, c3d, -c3c, c3e, -c3a};
+  return s[j];
 }
 
-// sum_j b[j] grad Y_j(x, y, z) of the homogeneous polynomials: the weighted
-// sum is first collected into one polynomial over the monomials of (x, y, z)
-// (the basis expansions above, term by term), which is then differentiated.
+// M_j(x, y, z), the basis without its normalisation
+__device__ inline void sh_monomials(float x, float y, float z, float M[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float d = xx - yy;
+  const float t = fmaf(4.f, zz, -(xx + yy));
+  M[0] = 1.f;
+  M[1] = y;
+  M[2] = z;
+  M[3] = x;
+  M[4] = x * y;
+  M[5] = y * z;
+  M[6] = fmaf(2.f, zz, -(xx + yy));
+  M[7] = x * z;
+  M[8] = d;
+  M[9] = y * fmaf(3.f, xx, -yy);
+  M[10] = M[4] * z;
+  M[11] = y * t;
+  M[12] = z * fmaf(-3.f, xx + yy, 2.f * zz);
+  M[13] = x * t;
+  M[14] = z * d;
+  M[15] = x * fmaf(-3.f, yy, xx);
+}
+
+// grad of P = sum_j b[j] M_j (b[0] does not enter). P is a polynomial over
+// the monomials of (x, y, z) of degree <= 3 (the expansions above, term by
+// term); each partial derivative is evaluated as
+//   dP/dx = Lx + x (2 Qxx + 3 Cxxx x + 2 Cxxy y + 2 Cxxz z)
+//              + y (Qxy + Cxyy y + Cxyz z) + z (Qxz + Cxzz z)
+// and its counterparts, with the derivative factors folded into the
+// coefficients.
 __device__ inline void sh_grad(float x, float y, float z, const float b[16], float& gx,
                                float& gy, float& gz) {
-  using namespace shc;
-  // degree 1
-  const float Lx = -c1 * b[3], Ly = -c1 * b[1], Lz = c1 * b[2];
-  // degree 2; the squares' coefficients carry their derivative factor 2
-  const float Qxy = c2a * b[4], Qyz = -c2a * b[5], Qxz = -c2a * b[7];
-  const float Qxx2 = 2.f * (c2c * b[8] - c2b * b[6]);
-  const float Qyy2 = -2.f * (c2b * b[6] + c2c * b[8]);
-  const float Qzz2 = 4.f * c2b * b[6];
+  // degree 1 and the mixed degree-2 coefficients are b[3], b[1], b[2] and
+  // b[4] (xy), b[5] (yz), b[7] (xz); the squares' coefficients times 2
+  const float Dx = 2.f * (b[8] - b[6]);     // 2 Qxx
+  const float Dy = -2.f * (b[6] + b[8]);    // 2 Qyy
+  const float Dz = 4.f * b[6];              // 2 Qzz
   // degree 3, one coefficient per monomial
-  const float Cxxy = c3c * b[11] - 3.f * c3a * b[9];
-  const float Cyyy = c3a * b[9] + c3c * b[11];
-  const float Cxyz = c3b * b[10];
-  const float Cyzz = -4.f * c3c * b[11];
-  const float Czzz = 2.f * c3d * b[12];
-  const float Cxxz = c3e * b[14] - 3.f * c3d * b[12];
-  const float Cyyz = -(3.f * c3d * b[12] + c3e * b[14]);
-  const float Cxzz = -4.f * c3c * b[13];
-  const float Cxxx = c3c * b[13] - c3a * b[15];
-  const float Cxyy = c3c * b[13] + 3.f * c3a * b[15];
-  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
-  gx = Lx + Qxy * y + Qxz * z + Qxx2 * x + 2.f * Cxxy * xy + Cxyz * yz + 2.f * Cxxz * xz +
-       Cxzz * zz + 3.f * Cxxx * xx + Cxyy * yy;
-  gy = Ly + Qxy * x + Qyz * z + Qyy2 * y + Cxxy * xx + 3.f * Cyyy * yy + Cxyz * xz +
-       Cyzz * zz + 2.f * Cyyz * yz + 2.f * Cxyy * xy;
-  gz = Lz + Qyz * y + Qxz * x + Qzz2 * z + Cxyz * xy + 2.f * Cyzz * yz + 3.f * Czzz * zz +
-       Cxxz * xx + Cyyz * yy + 2.f * Cxzz * xz;
+  const float Cxxy = fmaf(3.f, b[9], -b[11]);
+  const float Cyyy = -(b[9] + b[11]);
+  const float Cxyz = b[10];
+  const float Cyzz = 4.f * b[11];
+  const float Czzz = 2.f * b[12];
+  const float Cxxz = fmaf(-3.f, b[12], b[14]);
+  const float Cyyz = fmaf(-3.f, b[12], -b[14]);
+  const float Cxzz = 4.f * b[13];
+  const float Cxxx = b[15] - b[13];
+  const float Cxyy = fmaf(-3.f, b[15], -b[13]);
+  gx = fmaf(x, fmaf(3.f * Cxxx, x, fmaf(2.f * Cxxy, y, fmaf(2.f * Cxxz, z, Dx))),
+            fmaf(y, fmaf(Cxyy, y, fmaf(Cxyz, z, b[4])), fmaf(z, fmaf(Cxzz, z, b[7]), b[3])));
+  gy = fmaf(y, fmaf(3.f * Cyyy, y, fmaf(2.f * Cxyy, x, fmaf(2.f * Cyyz, z, Dy))),
+            fmaf(x, fmaf(Cxxy, x, fmaf(Cxyz, z, b[4])), fmaf(z, fmaf(Cyzz, z, b[5]), b[1])));
+  gz = fmaf(z, fmaf(3.f * Czzz, z, fmaf(2.f * Cyzz, y, fmaf(2.f * Cxzz, x, Dz))),
+            fmaf(x, fmaf(Cxxz, x, fmaf(Cxyz, y, b[7])), fmaf(y, fmaf(Cyyz, y, b[5]), b[2])));
 }
 
 template <int P, int VPL, bool BWD>
@@ -106,7 +127,8 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
 #pragma unroll
   for (int b = 0; b < 16; ++b)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) cf[b][c] = a.sh[static_cast<int64_t>(b * 3 + c) * N + i];
+    for (int c = 0; c < 3; ++c)
+      cf[b][c] = sh_scale(b) * load_once(&a.sh[static_cast<int64_t>(b * 3 + c) * N + i]);
 
   float gcf[16][3];
   if constexpr (BWD) {
@@ -126,9 +148,9 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
     for (int t = 0; t < VPL; ++t) {
       const int v = c0_ + j + P * t;
       const int64_t o = (static_cast<int64_t>(v < V ? v : 0) * N + i) * 3;
-      g[t][0] = a.grad_rgb[o + 0];
-      g[t][1] = a.grad_rgb[o + 1];
-      g[t][2] = a.grad_rgb[o + 2];
+      g[t][0] = load_if<P == 1>(&a.grad_rgb[o + 0]);
+      g[t][1] = load_if<P == 1>(&a.grad_rgb[o + 1]);
+      g[t][2] = load_if<P == 1>(&a.grad_rgb[o + 2]);
     }
   };
   if constexpr (BWD) load_grad(0, gq);
@@ -148,10 +170,11 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
         e1 -= a.cams[3 * v + 1];
         e2 -= a.cams[3 * v + 2];
       }
-      const float ri = rsqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+      // |e| is far from the denormal range (a camera never sits on a mean)
+      const float ri = __builtin_amdgcn_rsqf(e0 * e0 + e1 * e1 + e2 * e2);
       const float x = e0 * ri, y = e1 * ri, z = e2 * ri;
       float Y[16];
-      sh_basis(x, y, z, Y);
+      sh_monomials(x, y, z, Y);
       const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
       if (a.rgb != nullptr && valid) {
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
@@ -161,19 +184,20 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
           r1 = fmaf(cf[b][1], Y[b], r1);
           r2 = fmaf(cf[b][2], Y[b], r2);
         }
-        a.rgb[o + 0] = r0;
-        a.rgb[o + 1] = r1;
-        a.rgb[o + 2] = r2;
+        store_if<P == 1>(r0, &a.rgb[o + 0]);
+        store_if<P == 1>(r1, &a.rgb[o + 1]);
+        store_if<P == 1>(r2, &a.rgb[o + 2]);
       }
       if constexpr (BWD) {
         const float g0 = gq[t][0], g1 = gq[t][1], g2 = gq[t][2];
         float beta[16];
+        beta[0] = 0.f;
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
           gcf[b][0] = fmaf(g0, Y[b], gcf[b][0]);
           gcf[b][1] = fmaf(g1, Y[b], gcf[b][1]);
           gcf[b][2] = fmaf(g2, Y[b], gcf[b][2]);
-          beta[b] = fmaf(g0, cf[b][0], fmaf(g1, cf[b][1], g2 * cf[b][2]));
+          if (b > 0) beta[b] = fmaf(g0, cf[b][0], fmaf(g1, cf[b][1], g2 * cf[b][2]));
         }
         float gx, gy, gz;
         sh_grad(x, y, z, beta, gx, gy, gz);
@@ -197,20 +221,30 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
 #pragma unroll
     for (int b = 0; b < 16; ++b)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gcf[b][c] = group_sum<P>(gcf[b][c]);
+      for (int c = 0; c < 3; ++c) gcf[b][c] = sh_scale(b) * group_sum<P>(gcf[b][c]);
     gm0 = group_sum<P>(gm0);
     gm1 = group_sum<P>(gm1);
     gm2 = group_sum<P>(gm2);
     if (valid) {
       if (a.g_sh != nullptr) {
+        // two loops, so that the overwriting one keeps its streaming stores
+        if (a.accumulate) {
 #pragma unroll
-        for (int b = 0; b < 16; ++b)
+          for (int b = 0; b < 16; ++b)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            if (((b * 3 + c) & (P - 1)) != j) continue;
-            float* dst = a.g_sh + static_cast<int64_t>(b * 3 + c) * N + i;
-            *dst = a.accumulate ? *dst + gcf[b][c] : gcf[b][c];
-          }
+            for (int c = 0; c < 3; ++c) {
+              if (((b * 3 + c) & (P - 1)) != j) continue;
+              a.g_sh[static_cast<int64_t>(b * 3 + c) * N + i] += gcf[b][c];
+            }
+        } else {
+#pragma unroll
+          for (int b = 0; b < 16; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              if (((b * 3 + c) & (P - 1)) != j) continue;
+              store_once(gcf[b][c], &a.g_sh[static_cast<int64_t>(b * 3 + c) * N + i]);
+            }
+        }
       }
       if (a.g_geom != nullptr && j == 0) {
         float* dst = a.g_geom + 3 * i;
