@@ -23,13 +23,15 @@ constexpr double kInvPi = 0.318309886183790671537767526745028724;
 // cache policy keeps it from displacing what is still to be reused (the
 // cameras, the log table). The lobe records are read, and the lobe gradients
 // written, once per view chunk, so they are streamed only by the kernels of
-// launches whose views fit in one chunk (ONCE); with more chunks each record
-// is read again and each gradient read back for the next chunk's sums, and
-// both stay cached. The per-view colours and upstream gradients ([V][N][3])
-// are streamed where a wave's access covers whole cache lines (one lane per
-// primitive: 64 x 12 bytes); with several lanes per primitive a wave covers
-// 12 bytes of 64/P primitives, neighbouring waves share lines, and plain
-// accesses let the second one find its line cached.
+// launches whose views fit in one chunk and which do not add onto earlier
+// results (ONCE); with more chunks each record is read again and each
+// gradient read back for the next chunk's sums, and an accumulating caller
+// is going over the same primitives again, so all of it stays cached.
+// Stores, and the per-view colours and upstream gradients ([V][N][3]), are
+// streamed only where a wave's access covers whole cache lines (one lane per
+// primitive, e.g. 64 x 12 bytes per view); with several lanes per primitive
+// a wave covers a part of a line, the neighbouring wave the rest, and plain
+// accesses let the two parts meet in the cache.
 
 typedef float f32x4_nt __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2_nt __attribute__((ext_vector_type(2)));

@@ -111,7 +111,7 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
     // gradients of later view chunks accumulate onto the first chunk's
     const bool acc_mode = a.accumulate || v0 > 0;
     ViewSlots<VPL> sl;
-    slots_setup<P, VPL, BWD, BC>(a, i, v0, j, base, c0v, sl);
+    slots_setup<P, VPL, BWD, BC, ONCE>(a, i, v0, j, base, c0v, sl);
 
     // ---- lobes, P at a time: lane j owns lobe lc + j. The view slots travel
     // round the lane group (lane j takes over the slot of lane j + 1 after
@@ -315,12 +315,18 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         }
       }
 
-      // the owning lane writes its lobe's gradients
+      // the owning lane writes its lobe's gradients: as streaming data where
+      // each is written once (ONCE: acc_mode is false) and a wave's store
+      // covers whole cache lines (one lane per primitive); with P lanes a
+      // colour-weight row store covers 4 x 64/P bytes, and partial lines
+      // streamed out separately by neighbouring waves would cost extra HBM
+      // writes
+      constexpr bool kStreamGrads = ONCE && P == 1;
       if constexpr (BWD) {
         if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr) {
-            put4<ONCE>(a.g_shape, li,
+            put4<kStreamGrads>(a.g_shape, li,
                        make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l) * dlam_du,
                                    fmaf(nm.da, acc_G, acc_a) * da_du,
                                    fmaf(nm.dk, acc_G, acc_k) * dk_du, fmaf(nm.dz, acc_G, acc_z)),
@@ -329,16 +335,16 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           if (a.g_quat != nullptr) {
             const float xf[3] = {xf0, xf1, xf2}, zf[3] = {zf0, zf1, zf2};
             const float gx[3] = {ax0, ax1, ax2}, gz[3] = {az0, az1, az2};
-            put4<ONCE>(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
+            put4<kStreamGrads>(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
           }
           if (a.g_rgbw != nullptr)
-            put_rgbw<ONCE>(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1, acc_w2 * dw2,
-                           acc_mode);
+            put_rgbw<kStreamGrads>(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1,
+                                   acc_w2 * dw2, acc_mode);
         }
       }
     }
 
-    slots_finish<P, VPL, BWD, BC>(a, i, valid, v0, j, acc_mode, sl);
+    slots_finish<P, VPL, BWD, BC, ONCE>(a, i, valid, v0, j, acc_mode, sl);
   }
 }
 
@@ -346,8 +352,10 @@ template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC, bo
 // One lane and one view per primitive run three waves per SIMD (the few spills
 // land in the once-per-lobe preparation), and so do broadcast views; the other
 // mappings keep two, where the full register budget pays more than a third wave.
-// ONCE: all views fit in one chunk, so the lobe records are read and the
-// lobe gradients written exactly once, both as streaming data.
+// ONCE: all views fit in one chunk and nothing accumulates onto earlier
+// results, so the lobe records are read and the outputs written exactly once
+// (the records then stream; the gradients and the per-view data too with one
+// lane per primitive).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     BC ? NASG_BC_WAVES : (P == 1 && VPL == 1 ? 3 : 2))))
 void nasg_kernel(const NasgArgs a) {
@@ -459,7 +467,10 @@ template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
 static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
   const int64_t threads = a.n * P;
   const int64_t grid = (threads + block - 1) / block;
-  if (a.v <= (BC ? VPL : P * VPL)) {
+  // ONCE kernels write every output once and read every record once: no
+  // accumulation onto earlier results and all views in one chunk (so their
+  // acc_mode is always false)
+  if (!a.accumulate && a.v <= (BC ? VPL : P * VPL)) {
     hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, true>),
                        dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
   } else {

@@ -100,7 +100,7 @@ struct ViewSlots {
 // broadcast): every lane of the group holds the same views v0 + t, t < VPL,
 // and only lane 0's colours start from c0 (the group's partial colours are
 // summed after the lobes).
-template <int P, int VPL, bool BWD, bool BC = false>
+template <int P, int VPL, bool BWD, bool BC = false, bool STREAM = false>
 __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0, int j,
                                             const double (&base)[3], const float (&c0)[3],
                                             ViewSlots<VPL>& s) {
@@ -133,9 +133,9 @@ __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0
     if constexpr (BWD) {
       if (s.has[t]) {
         const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
-        s.gr[t][0] = load_if<P == 1>(&a.grad_rgb[o + 0]);
-        s.gr[t][1] = load_if<P == 1>(&a.grad_rgb[o + 1]);
-        s.gr[t][2] = load_if<P == 1>(&a.grad_rgb[o + 2]);
+        s.gr[t][0] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 0]);
+        s.gr[t][1] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 1]);
+        s.gr[t][2] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 2]);
       } else {
         s.gr[t][0] = s.gr[t][1] = s.gr[t][2] = 0.f;
       }
@@ -166,7 +166,7 @@ __device__ __forceinline__ void slot_pass(ViewSlots<VPL>& s, int t, int rot_addr
 // and direction gradients are first summed over its lanes (each lane then
 // holds the totals of all VPL views); lane t % P writes view t's colour, and
 // the c0 and mean gradients are not summed over lanes again.
-template <int P, int VPL, bool BWD, bool BC = false>
+template <int P, int VPL, bool BWD, bool BC = false, bool STREAM = false>
 __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool valid, int v0,
                                              int j, bool acc_mode, ViewSlots<VPL>& s) {
   const int64_t N = a.n;
@@ -185,9 +185,9 @@ __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool 
     for (int t = 0; t < VPL; ++t) {
       if (!s.has[t] || (BC && j != t % P)) continue;
       const int64_t o = (static_cast<int64_t>(BC ? v0 + t : v0 + j + P * t) * N + i) * 3;
-      store_if<P == 1>(s.col[t][0], &a.rgb[o + 0]);
-      store_if<P == 1>(s.col[t][1], &a.rgb[o + 1]);
-      store_if<P == 1>(s.col[t][2], &a.rgb[o + 2]);
+      store_if<STREAM && P == 1>(s.col[t][0], &a.rgb[o + 0]);
+      store_if<STREAM && P == 1>(s.col[t][1], &a.rgb[o + 1]);
+      store_if<STREAM && P == 1>(s.col[t][2], &a.rgb[o + 2]);
     }
   }
   if constexpr (BWD) {
@@ -351,42 +351,47 @@ __device__ __forceinline__ float4 frame_grad(const float (&f)[6], const float (&
   }
 }
 
-// Adds or writes a float4 gradient. FINAL: the write is the last one, so
-// it streams (the kernels of single-chunk launches); with more view chunks
-// the first chunk's write is read back by the next one and stays cached. The
-// adding branch stores the four words one by one: were both branches one
-// 16-byte store of the same address, the compiler would merge them into a
-// single plain store.
-template <bool FINAL>
+// Adds or writes a float4 gradient. STREAM: the kernel writes every
+// gradient exactly once (one view chunk, no accumulation, so acc_mode is
+// false) and its stores cover whole cache lines; the write is then
+// streaming data. The two forms are chosen at compile time: a run-time
+// choice between a plain and a streaming store of the same address would be
+// merged by the compiler into one plain store.
+template <bool STREAM>
 __device__ __forceinline__ void put4(float* base, int64_t li, float4 g, bool acc_mode) {
-  float* dst = base + 4 * li;
-  if (acc_mode) {
-    dst[0] += g.x;
-    dst[1] += g.y;
-    dst[2] += g.z;
-    dst[3] += g.w;
-  } else if constexpr (FINAL) {
+  float4* dst = reinterpret_cast<float4*>(base) + li;
+  if constexpr (STREAM) {
     store_once(f32x4_nt{g.x, g.y, g.z, g.w}, reinterpret_cast<f32x4_nt*>(dst));
   } else {
-    *reinterpret_cast<float4*>(dst) = g;
+    if (acc_mode) {
+      const float4 o = *dst;
+      g.x += o.x;
+      g.y += o.y;
+      g.z += o.z;
+      g.w += o.w;
+    }
+    *dst = g;
   }
 }
 
 // Adds or writes a per-lobe colour-weight gradient in the channel-planar
-// layout [K][3][N] (FINAL as for put4).
-template <bool FINAL>
+// layout [K][3][N] (STREAM as for put4). The three old values are loaded
+// before any store: N is a run-time stride, so a store to one channel would
+// otherwise have to complete before the next channel's load.
+template <bool STREAM>
 __device__ __forceinline__ void put_rgbw(float* g_rgbw, int lobe, int64_t N, int64_t i, float r0,
                                          float r1, float r2, bool acc_mode) {
   float* dst = g_rgbw + static_cast<int64_t>(lobe) * 3 * N + i;
-  if (acc_mode) {
-    dst[0] += r0;
-    dst[N] += r1;
-    dst[2 * N] += r2;
-  } else if constexpr (FINAL) {
+  if constexpr (STREAM) {
     store_once(r0, dst);
     store_once(r1, dst + N);
     store_once(r2, dst + 2 * N);
   } else {
+    if (acc_mode) {
+      r0 += dst[0];
+      r1 += dst[N];
+      r2 += dst[2 * N];
+    }
     dst[0] = r0;
     dst[N] = r1;
     dst[2 * N] = r2;

@@ -25,9 +25,9 @@
 // only the M_j: rgb = sum c'_j M_j, the direction gradient is that of
 // sum_j beta'_j M_j with beta'_j = g . c'_j (= s_j g . c_j), and the
 // coefficient gradient sum_v g M_j is scaled by s_j once, when it is written.
-// Coefficients and their gradients, read and written once per launch, are
-// streamed; so are the per-view colours and upstream gradients with one lane
-// per primitive, whose accesses then cover whole cache lines.
+// The coefficients, read once per launch, are streamed; so are the
+// coefficient gradients, colours and upstream gradients with one lane per
+// primitive, whose accesses then cover whole cache lines.
 #include <hip/hip_runtime.h>
 
 #include "nasg_device.hpp"
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void sh3_kernel(const ShArgs a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               if (((b * 3 + c) & (P - 1)) != j) continue;
-              store_once(gcf[b][c], &a.g_sh[static_cast<int64_t>(b * 3 + c) * N + i]);
+              store_if<P == 1>(gcf[b][c], &a.g_sh[static_cast<int64_t>(b * 3 + c) * N + i]);
             }
         }
       }
