@@ -21,18 +21,15 @@ constexpr double kInvPi = 0.318309886183790671537767526745028724;
 // ---------------------------------------------------------------- storage
 // Data that a launch touches once is accessed nontemporally: the streaming
 // cache policy keeps it from displacing what is still to be reused (the
-// cameras, the log table). The lobe records are read, and the lobe gradients
-// written, once per view chunk, so they are streamed only by the kernels of
-// launches whose views fit in one chunk and which do not add onto earlier
-// results (ONCE); with more chunks each record is read again and each
-// gradient read back for the next chunk's sums, and an accumulating caller
-// is going over the same primitives again, so all of it stays cached.
-// Stores, and the per-view colours and upstream gradients ([V][N][3]), are
-// streamed only where a wave's access covers whole cache lines (one lane per
-// primitive, e.g. 64 x 12 bytes per view); with several lanes per primitive
-// a wave covers a part of a line, the neighbouring wave the rest, and plain
-// accesses let the two parts meet in the cache.
-
+// cameras, the log table). The appearance kernels do so in their streaming
+// flavour (ONCE), used where it is safe and pays: one lane per primitive, so
+// that a wave's access covers whole cache lines (with P lanes a wave covers
+// part of a line, e.g. 4 x 64/P bytes of a colour-weight row, its neighbour
+// the rest, and a streamed line can be gone before the second part is read
+// or be written out twice), and a launch that reads every lobe record and
+// writes every output once (all views in one chunk, no accumulation onto
+// earlier results; otherwise later chunks, or the accumulating caller's next
+// launch, read the same data again and it should stay cached).
 typedef float f32x4_nt __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2_nt __attribute__((ext_vector_type(2)));
 

@@ -315,18 +315,13 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
         }
       }
 
-      // the owning lane writes its lobe's gradients: as streaming data where
-      // each is written once (ONCE: acc_mode is false) and a wave's store
-      // covers whole cache lines (one lane per primitive); with P lanes a
-      // colour-weight row store covers 4 x 64/P bytes, and partial lines
-      // streamed out separately by neighbouring waves would cost extra HBM
-      // writes
-      constexpr bool kStreamGrads = ONCE && P == 1;
+      // the owning lane writes its lobe's gradients, as streaming data in the
+      // ONCE flavour (each written once: acc_mode is false there)
       if constexpr (BWD) {
         if (valid && own) {
           const int64_t li = static_cast<int64_t>(lc + j) * N + i;
           if (a.g_shape != nullptr) {
-            put4<kStreamGrads>(a.g_shape, li,
+            put4<ONCE>(a.g_shape, li,
                        make_float4(fmaf(nm.dl, acc_G, 2.f * acc_l) * dlam_du,
                                    fmaf(nm.da, acc_G, acc_a) * da_du,
                                    fmaf(nm.dk, acc_G, acc_k) * dk_du, fmaf(nm.dz, acc_G, acc_z)),
@@ -335,10 +330,10 @@ __device__ __forceinline__ void nasg_body(const NasgArgs& a, int64_t prim, int j
           if (a.g_quat != nullptr) {
             const float xf[3] = {xf0, xf1, xf2}, zf[3] = {zf0, zf1, zf2};
             const float gx[3] = {ax0, ax1, ax2}, gz[3] = {az0, az1, az2};
-            put4<kStreamGrads>(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
+            put4<ONCE>(a.g_quat, li, frame_grad<ANG>(f, xf, zf, gx, gz), acc_mode);
           }
           if (a.g_rgbw != nullptr)
-            put_rgbw<kStreamGrads>(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1,
+            put_rgbw<ONCE>(a.g_rgbw, lc + j, N, i, acc_w0 * dw0, acc_w1 * dw1,
                                    acc_w2 * dw2, acc_mode);
         }
       }
@@ -352,13 +347,13 @@ template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC, bo
 // One lane and one view per primitive run three waves per SIMD (the few spills
 // land in the once-per-lobe preparation), and so do broadcast views; the other
 // mappings keep two, where the full register budget pays more than a third wave.
-// ONCE: all views fit in one chunk and nothing accumulates onto earlier
-// results, so the lobe records are read and the outputs written exactly once
-// (the records then stream; the gradients and the per-view data too with one
-// lane per primitive).
+// ONCE (one lane per primitive only): all views fit in one chunk and nothing
+// accumulates onto earlier results, so the lobe records are read and every
+// output is written exactly once, all as streaming data.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     BC ? NASG_BC_WAVES : (P == 1 && VPL == 1 ? 3 : 2))))
 void nasg_kernel(const NasgArgs a) {
+  static_assert(!ONCE || P == 1, "the streaming flavour has one lane per primitive");
   __shared__ LogEntry ltab[kLogEntries];
   load_log_table(ltab);
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -467,16 +462,19 @@ template <int P, int VPL, bool BWD, bool BF16, bool ANG, bool NOCAR, bool BC>
 static hipError_t launch_one(const NasgArgs& a, int block, hipStream_t s) {
   const int64_t threads = a.n * P;
   const int64_t grid = (threads + block - 1) / block;
-  // ONCE kernels write every output once and read every record once: no
-  // accumulation onto earlier results and all views in one chunk (so their
-  // acc_mode is always false)
-  if (!a.accumulate && a.v <= (BC ? VPL : P * VPL)) {
-    hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, true>),
-                       dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, false>),
-                       dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
+  // The streaming flavour (ONCE): one lane per primitive, so that a wave's
+  // accesses cover whole cache lines, and a launch that reads every record
+  // and writes every output once: all views in one chunk and no accumulation
+  // onto earlier results (so acc_mode is always false in it).
+  if constexpr (P == 1) {
+    if (!a.accumulate && a.v <= VPL) {
+      hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, true>),
+                         dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
+      return hipGetLastError();
+    }
   }
+  hipLaunchKernelGGL((nasg_kernel<P, VPL, BWD, BF16, ANG, NOCAR, BC, false>),
+                     dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 

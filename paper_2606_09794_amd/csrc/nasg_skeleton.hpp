@@ -133,9 +133,9 @@ __device__ __forceinline__ void slots_setup(const NasgArgs& a, int64_t i, int v0
     if constexpr (BWD) {
       if (s.has[t]) {
         const int64_t o = (static_cast<int64_t>(v) * N + i) * 3;
-        s.gr[t][0] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 0]);
-        s.gr[t][1] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 1]);
-        s.gr[t][2] = load_if<STREAM && P == 1>(&a.grad_rgb[o + 2]);
+        s.gr[t][0] = load_if<STREAM>(&a.grad_rgb[o + 0]);
+        s.gr[t][1] = load_if<STREAM>(&a.grad_rgb[o + 1]);
+        s.gr[t][2] = load_if<STREAM>(&a.grad_rgb[o + 2]);
       } else {
         s.gr[t][0] = s.gr[t][1] = s.gr[t][2] = 0.f;
       }
@@ -185,9 +185,9 @@ __device__ __forceinline__ void slots_finish(const NasgArgs& a, int64_t i, bool 
     for (int t = 0; t < VPL; ++t) {
       if (!s.has[t] || (BC && j != t % P)) continue;
       const int64_t o = (static_cast<int64_t>(BC ? v0 + t : v0 + j + P * t) * N + i) * 3;
-      store_if<STREAM && P == 1>(s.col[t][0], &a.rgb[o + 0]);
-      store_if<STREAM && P == 1>(s.col[t][1], &a.rgb[o + 1]);
-      store_if<STREAM && P == 1>(s.col[t][2], &a.rgb[o + 2]);
+      store_if<STREAM>(s.col[t][0], &a.rgb[o + 0]);
+      store_if<STREAM>(s.col[t][1], &a.rgb[o + 1]);
+      store_if<STREAM>(s.col[t][2], &a.rgb[o + 2]);
     }
   }
   if constexpr (BWD) {
@@ -353,8 +353,8 @@ __device__ __forceinline__ float4 frame_grad(const float (&f)[6], const float (&
 
 // Adds or writes a float4 gradient. STREAM: the kernel writes every
 // gradient exactly once (one view chunk, no accumulation, so acc_mode is
-// false) and its stores cover whole cache lines; the write is then
-// streaming data. The two forms are chosen at compile time: a run-time
+// false) and its stores cover whole cache lines (one lane per primitive);
+// the write is then streaming data. The two forms are chosen at compile time: a run-time
 // choice between a plain and a streaming store of the same address would be
 // merged by the compiler into one plain store.
 template <bool STREAM>
